@@ -1,0 +1,36 @@
+"""FP64 oracle: the rule of thumb for the preconditioner size (section 4.3).
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+
+runtime(k) ~ n^3 [ (k_min/k)^m + (k/n)^2 ]               (Eq. 7)
+k_RoT      = (k_min^m m n^2 / 2)^(1/(2+m))                (Eq. 8)
+Defaults m = 1, k_min = 100; the 1%-baseline is k = n/100.
+
+Pin (tests/test_oracle_rot.py): k_RoT equals the numerical minimiser of
+runtime(k) over k in [1, n].
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def runtime_model(k, n, k_min=100.0, m=1.0):
+    k = np.asarray(k, dtype=np.float64)
+    return float(n) ** 3 * ((k_min / k) ** m + (k / n) ** 2)
+
+
+def k_rule_of_thumb(n, k_min=100.0, m=1.0):
+    return (k_min ** m * m * float(n) ** 2 / 2.0) ** (1.0 / (2.0 + m))
+
+
+def k_one_percent(n):
+    return n / 100.0
+
+
+def fit_power_law(k, iters, n):
+    """Fit #/n = (k_min/k)^m by least squares in log-log space: returns (k_min, m)."""
+    lk = np.log(np.asarray(k, dtype=np.float64))
+    ly = np.log(np.asarray(iters, dtype=np.float64) / n)
+    A = np.stack([np.ones_like(lk), -lk], axis=1)
+    (c0, m), *_ = np.linalg.lstsq(A, ly, rcond=None)
+    return float(np.exp(c0 / m)), float(m)
