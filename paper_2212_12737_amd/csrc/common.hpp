@@ -1,0 +1,294 @@
+// Internal declarations shared by the translation units of libffkrr.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/ffkrr.h"
+
+namespace ffk {
+
+// ---------------------------------------------------------------- errors ----
+struct Error : std::runtime_error {
+  ffk_status status;
+  Error(ffk_status s, const std::string& m) : std::runtime_error(m), status(s) {}
+};
+
+[[noreturn]] inline void fail(ffk_status s, const std::string& msg) { throw Error(s, msg); }
+
+inline void hip_check(hipError_t e, const char* what, const char* file, int line) {
+  if (e != hipSuccess) {
+    char buf[512];
+    snprintf(buf, sizeof(buf), "%s failed at %s:%d: %s", what, file, line, hipGetErrorString(e));
+    fail(e == hipErrorOutOfMemory ? FFK_ERR_OOM : FFK_ERR_HIP, buf);
+  }
+}
+#define HIPCHK(x) ::ffk::hip_check((x), #x, __FILE__, __LINE__)
+#define LAUNCHCHK() ::ffk::hip_check(hipGetLastError(), "kernel launch", __FILE__, __LINE__)
+
+inline void require(bool ok, const std::string& msg) {
+  if (!ok) fail(FFK_ERR_ARG, msg);
+}
+
+// ------------------------------------------------------- device buffers ----
+// Owning device allocation; released on destruction.
+class DBuf {
+ public:
+  DBuf() = default;
+  explicit DBuf(size_t bytes) { alloc(bytes); }
+  ~DBuf() { release(); }
+  DBuf(const DBuf&) = delete;
+  DBuf& operator=(const DBuf&) = delete;
+  DBuf(DBuf&& o) noexcept : p_(o.p_), n_(o.n_) { o.p_ = nullptr; o.n_ = 0; }
+  DBuf& operator=(DBuf&& o) noexcept {
+    if (this != &o) { release(); p_ = o.p_; n_ = o.n_; o.p_ = nullptr; o.n_ = 0; }
+    return *this;
+  }
+  void alloc(size_t bytes) {
+    release();
+    if (bytes == 0) bytes = 256;
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      char buf[160];
+      snprintf(buf, sizeof(buf), "hipMalloc of %zu bytes failed: %s", bytes, hipGetErrorString(e));
+      fail(FFK_ERR_OOM, buf);
+    }
+    p_ = p;
+    n_ = bytes;
+  }
+  // Grow to at least `bytes` (contents are not preserved).
+  void ensure(size_t bytes) { if (n_ < bytes) alloc(bytes); }
+  void release() {
+    if (p_) (void)hipFree(p_);
+    p_ = nullptr;
+    n_ = 0;
+  }
+  template <class T> T* as() const { return static_cast<T*>(p_); }
+  void* get() const { return p_; }
+  size_t bytes() const { return n_; }
+  explicit operator bool() const { return p_ != nullptr; }
+
+ private:
+  void* p_ = nullptr;
+  size_t n_ = 0;
+};
+
+// Pinned host staging buffer for small readbacks.
+class HBuf {
+ public:
+  HBuf() = default;
+  ~HBuf() { if (p_) (void)hipHostFree(p_); }
+  HBuf(const HBuf&) = delete;
+  HBuf& operator=(const HBuf&) = delete;
+  void ensure(size_t bytes) {
+    if (n_ >= bytes) return;
+    if (p_) (void)hipHostFree(p_);
+    p_ = nullptr;
+    HIPCHK(hipHostMalloc(&p_, bytes, hipHostMallocDefault));
+    n_ = bytes;
+  }
+  template <class T> T* as() const { return static_cast<T*>(p_); }
+
+ private:
+  void* p_ = nullptr;
+  size_t n_ = 0;
+};
+
+inline int cdiv(int64_t a, int64_t b) { return static_cast<int>((a + b - 1) / b); }
+
+// ----------------------------------------------------------- bf16 helpers ----
+typedef uint16_t bf16_t;   // raw storage of a bfloat16
+
+__host__ __device__ inline bf16_t f2bf(float x) {
+  // round to nearest even (inputs are finite here)
+  uint32_t u;
+  memcpy(&u, &x, 4);
+  uint32_t r = u + 0x7FFFu + ((u >> 16) & 1u);
+  return static_cast<bf16_t>(r >> 16);
+}
+__host__ __device__ inline float bf2f(bf16_t h) {
+  uint32_t u = static_cast<uint32_t>(h) << 16;
+  float x;
+  memcpy(&x, &u, 4);
+  return x;
+}
+
+// ------------------------------------------------------------- handles ----
+}  // namespace ffk
+
+struct ffk_ctx {
+  int device = 0;
+  std::string last_error;
+  ffk::HBuf host_scratch;          // pinned readback area
+};
+
+namespace ffk {
+
+// Coefficients of the kernel for one storage precision: dA = a(r) - a(0),
+// B = b(r), as N x N row-major matrices.
+struct CoeffSet {
+  DBuf dA_hi, dA_lo;   // FP64: dA_hi holds double; FP32: float; BF16: hi (+lo for BF16X3)
+  DBuf B;              // FP64: double, otherwise float
+  bool ready = false;
+};
+
+// Per-precision MVM workspaces.
+struct MvmWork {
+  DBuf U64;            // N x D double  (J v)
+  DBuf pd;             // N double      (x_c,j . u_j)
+  DBuf s;              // D double      (column sums of U)
+  DBuf spart;          // partials of s
+  DBuf U32;            // N x D float
+  DBuf Uh, Ul;         // N x D bf16
+  DBuf UTh, UTl;       // D x N bf16
+  DBuf Wn64;           // N x N double  (-W)
+  DBuf Wn32;           // N x N float
+  DBuf Wnh, Wnl;       // N x N bf16
+  DBuf wpart;          // N x tilesN double (row-sum partials of W)
+  DBuf G;              // N x D double
+};
+
+}  // namespace ffk
+
+struct ffk_system {
+  ffk_ctx* ctx = nullptr;
+  int64_t N = 0;
+  int32_t M = 0;
+  int64_t D = 0;
+  int64_t n = 0;
+  double sigma = 10.0;
+  double a0 = 0.0;          // a(0) = 5/(3 sigma^2)
+  double bcoef = 0.0;       // 25/(3 sigma^4)
+  ffk::DBuf R;              // N x M x 3 double
+  ffk::DBuf pairs;          // D int32: (p << 16) | q
+  ffk::DBuf X;              // N x D double (uncentred)
+  ffk::DBuf xmean;          // D double
+  ffk::DBuf Xc;             // N x D double (centred)
+  ffk::DBuf sqn;            // N double (|x_c|^2)
+  ffk::DBuf Xc32;           // N x D float
+  ffk::DBuf Xch, Xcl;       // N x D bf16 hi/lo
+  ffk::DBuf XcTh, XcTl;     // D x N bf16 hi/lo
+  ffk::CoeffSet coef[4];    // indexed by ffk_precision
+  ffk::MvmWork work;
+  double max_diag = -1.0;   // max diag(K), computed on demand
+};
+
+struct ffk_precond {
+  ffk_ctx* ctx = nullptr;
+  int64_t n = 0, k = 0, k_eff = 0;
+  double lambda = 0.0;
+  int32_t store = FFK_FP64;
+  ffk::DBuf L;              // n x k column-major (double or float)
+  ffk::DBuf Finv;           // k x k row-major lower-triangular inverse of chol(core)
+  ffk::DBuf FinvT;          // its transpose, row-major
+  ffk::DBuf y, t1, t;       // k-vectors
+  int64_t bytes = 0;
+};
+
+struct ffk_mlp {
+  ffk_ctx* ctx = nullptr;
+  int32_t D = 0, H = 0;
+  int64_t nparam = 0;
+  ffk::DBuf theta;          // params, then mean (D), inv_std (D), out offset/scale (2)
+  ffk::DBuf m, v;           // Adam moments
+  int64_t t = 0;            // Adam step count
+  ffk::DBuf work;           // activations and temporaries
+  ffk::DBuf wbf;            // bf16 copies of W1, W2 for inference
+  bool wbf_valid = false;
+};
+
+namespace ffk {
+
+// ---------------------------------------------------- internal interfaces ----
+// descriptor.hip
+void descriptor_build(ffk_system* sys, const double* R, hipStream_t st);
+void ensure_coeffs(ffk_system* sys, int prec, hipStream_t st);
+void ensure_lowp_descriptor(ffk_system* sys, int prec, hipStream_t st);
+
+// mvm.hip
+void kernel_mvm(ffk_system* sys, const double* v, double* y, double shift, int prec, hipStream_t st);
+void kernel_mvm_phases(ffk_system* sys, const double* v, double* y, double shift, int prec, int iters,
+                       double* ms, hipStream_t st);
+void kernel_predict(const ffk_system* train, const ffk_system* test, const double* alpha,
+                    double* F, hipStream_t st);
+
+// columns.hip
+// out[:, c] = K[:, cols[c]] + shift * e_{cols[c]}, column-major with leading dimension ldo.
+void kernel_columns(const ffk_system* sys, const int64_t* cols, int64_t k, double* out,
+                    int64_t ldo, double shift, hipStream_t st);
+void kernel_diag(const ffk_system* sys, double* d, hipStream_t st);
+double max_diag(ffk_system* sys, hipStream_t st);
+
+// dense.hip : FP64 GEMM (C = alpha A B^T + beta C on strided views) and factorizations
+struct View64 {
+  const double* p;
+  int64_t s0, s1;   // element (i, j) at p[i * s0 + j * s1]
+};
+void gemm64(int M, int N, int K, double alpha, View64 A, View64 B, double beta, double* C,
+            int64_t scm, int64_t scn, bool lower_only, hipStream_t st);
+// Lower Cholesky in place of the n x n column-major matrix A (lda). Returns the
+// index of the first failing pivot or -1.
+int64_t potrf_lower(double* A, int64_t n, int64_t lda, hipStream_t st);
+// In-place inverse of the lower-triangular n x n column-major matrix A.
+void trtri_lower(double* A, int64_t n, int64_t lda, hipStream_t st);
+
+// reduce.hip -- deterministic two-stage reductions; `part` holds >= kRedParts doubles.
+constexpr int kRedParts = 1024;
+void dot64(const double* a, const double* b, int64_t n, double* part, double* out_dev, hipStream_t st);
+void reduce_max64(const double* a, int64_t n, double* part, double* out_dev, hipStream_t st);
+
+// select.hip
+void select_uniform(const ffk_system* sys, int64_t k, uint64_t seed, int64_t* idx, hipStream_t st);
+void select_weighted(int64_t n, const double* w, int64_t k, uint64_t seed, int stream_id,
+                     int64_t* idx, hipStream_t st);
+int64_t select_pivchol(ffk_system* sys, int64_t k, int64_t* idx, hipStream_t st);
+void leverage_estimate(ffk_system* sys, const int64_t* pilot, int64_t s, double lambda,
+                       double* tau, hipStream_t st);
+
+// precond.hip
+// Incomplete Cholesky with pivots forced to idx (order kept) of K + shift I.
+// L: n x k column-major double.  kept (host, k) receives which columns survived.
+int64_t icd_forced(ffk_system* sys, const int64_t* idx, int64_t k, double shift, double* L,
+                   std::vector<char>* kept, hipStream_t st);
+ffk_precond* precond_build(ffk_system* sys, const int64_t* idx, int64_t k, double lambda,
+                           int store, bool* dropped, hipStream_t st);
+void precond_apply(const ffk_precond* P, const double* r, double* z, hipStream_t st);
+
+// pcg.hip
+ffk_status pcg_solve(ffk_system* sys, const ffk_precond* P, const double* F, double* alpha,
+                     const ffk_pcg_opts* o, ffk_pcg_report* rep, hipStream_t st);
+
+// rls.hip
+void exact_rls(ffk_system* sys, double lambda, double* tau, hipStream_t st);
+
+// mlp.hip
+ffk_mlp* mlp_create(int32_t D, int32_t H, uint64_t seed);
+void mlp_forward(const ffk_mlp* net, const float* X, int64_t B, float* out, int prec, hipStream_t st);
+void mlp_grad(ffk_mlp* net, const float* X, const float* y, int64_t B, float* loss, float* grad,
+              hipStream_t st);
+void mlp_adam(ffk_mlp* net, const float* grad, float lr, hipStream_t st);
+void mlp_scores(const ffk_mlp* net, const ffk_system* sys, double* scores, hipStream_t st);
+
+// rng shared by host and device code of the library
+__host__ __device__ inline uint64_t splitmix64_at(uint64_t seed, uint64_t counter) {
+  uint64_t z = seed + (counter + 1ull) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+__host__ __device__ inline double uniform01_at(uint64_t seed, uint64_t stream, uint64_t i) {
+  uint64_t z = splitmix64_at(seed, (stream << 40) + i);
+  return static_cast<double>((z >> 11) + 1ull) * 0x1.0p-53;
+}
+
+}  // namespace ffk

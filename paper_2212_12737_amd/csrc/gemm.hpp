@@ -1,0 +1,333 @@
+// MFMA GEMM engines for gfx950.
+//
+// Both engines compute a BM x BN tile of  acc = sum_k A(m, k) B(n, k)  (an
+// "A B^T" product) with 256 threads = 4 wave64s in a 2 x 2 arrangement; each
+// wave owns a (BM/2) x (BN/2) sub-tile made of 16 x 16 MFMA blocks.  Operand
+// lane layout (all three instructions): lane l supplies row l%16 and the
+// K-slice l/16.  Output lane layout: lane l, register v holds column l%16 and
+// row 4*(l/16) + v for the FP32-output instructions, but row 4*v + l/16 for
+// v_mfma_f64_16x16x4_f64.
+// After the K loop the engine hands the accumulators to an epilogue functor,
+// which does all stores (and any fused elementwise work and row reductions).
+//
+// ScalarEngine<T>: T = double (v_mfma_f64_16x16x4_f64) or float
+//   (v_mfma_f32_16x16x4_f32).  One operand element per lane per instruction, so
+//   operands may be K-contiguous or M-contiguous strided views; LDS tiles are
+//   stored [k][m] with 16 elements of padding per row.  Bounds are checked.
+//
+// Bf16Engine: v_mfma_f32_16x16x32_bf16, FP32 accumulation, optional split
+//   mode (X3) that adds hi*hi + hi*lo + lo*hi.  Operands are K-contiguous bf16
+//   arrays whose row count is padded to a multiple of BM (or BN) and whose
+//   leading dimension is padded to a multiple of BK with zeros, so tiles are
+//   loaded with unpredicated 16-byte vectors.  LDS tiles are [m][k] with 8
+//   elements of row padding, which makes the 16-byte operand reads of one
+//   16-lane group hit distinct banks.
+#pragma once
+
+#include "common.hpp"
+
+namespace ffk {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef uint32_t u4 __attribute__((ext_vector_type(4)));
+
+template <typename T> struct Mfma16;
+template <> struct Mfma16<double> {
+  typedef d4 acc_t;
+  __device__ static inline acc_t run(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+};
+template <> struct Mfma16<float> {
+  typedef f4 acc_t;
+  __device__ static inline acc_t run(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+};
+
+__device__ inline f4 mfma_bf16(u4 a, u4 b, f4 c) {
+  bf8 av = __builtin_bit_cast(bf8, a);
+  bf8 bv = __builtin_bit_cast(bf8, b);
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, c, 0, 0, 0);
+}
+
+// Coordinates of accumulator element (tm, tn, v) for this lane, relative to the tile.
+struct FragCoord {
+  int wm0, wn0, lane;   // absolute origin of this wave's sub-tile
+  int m0, n0;           // absolute origin of the block tile
+  bool f64;             // FP64 MFMA output layout
+  __device__ inline int row(int tm, int v) const {
+    return wm0 + tm * 16 + (f64 ? 4 * v + (lane >> 4) : 4 * (lane >> 4) + v);
+  }
+  __device__ inline int col(int tn) const { return wn0 + tn * 16 + (lane & 15); }
+};
+
+// Operand segment of a scalar GEMM: element (m, k) at p[m*s0 + k*s1].  The
+// stored type TI may be narrower than the compute type (float -> double is exact).
+template <typename TI> struct SegS {
+  const TI* A; int64_t sa0, sa1;
+  const TI* B; int64_t sb0, sb1;
+  int K;
+};
+
+template <typename TI> struct ScalarArgs {
+  int M, N;
+  int nseg;
+  SegS<TI> seg[2];
+  bool lower_only;   // skip tiles whose columns all exceed their rows
+  bool a_lower;      // A(m, k) = 0 for k > m (restricts the K range per tile)
+};
+
+// ---------------------------------------------------------------------------
+// Scalar-operand MFMA engine (FP64 / FP32)
+// ---------------------------------------------------------------------------
+template <typename T, int BM, int BN, int BK, bool AKC, bool BKC, class Epi, typename TI = T>
+__global__ __launch_bounds__(256) void gemm_scalar_kernel(ScalarArgs<TI> g, Epi epi) {
+  constexpr int PAD = 16;
+  constexpr int EA = BM * BK / 256;
+  constexpr int EB = BN * BK / 256;
+  constexpr int TM = BM / 32;   // 16x16 blocks per wave along M
+  constexpr int TN = BN / 32;
+  typedef typename Mfma16<T>::acc_t acc_t;
+  __shared__ T As[2][BK][BM + PAD];
+  __shared__ T Bs[2][BK][BN + PAD];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  if (g.lower_only && n0 > m0 + BM - 1) return;
+  const int wm0 = (wave >> 1) * (BM / 2), wn0 = (wave & 1) * (BN / 2);
+
+  // tiles of every segment, walked as one sequence
+  int kend0 = g.seg[0].K;
+  if (g.a_lower) kend0 = min(kend0, m0 + BM);
+  const int t0 = (kend0 + BK - 1) / BK;
+  const int t1 = g.nseg > 1 ? (g.seg[1].K + BK - 1) / BK : 0;
+  const int T_ = t0 + t1;
+
+  acc_t acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
+
+  T ra[EA], rb[EB];
+  auto load = [&](int t) {
+    const SegS<TI>& s = (t < t0) ? g.seg[0] : g.seg[1];
+    const bool tri = g.a_lower && t < t0;
+    const int k0 = (t < t0 ? t : t - t0) * BK;
+    const int Kl = (t < t0) ? kend0 : s.K;
+#pragma unroll
+    for (int i = 0; i < EA; ++i) {
+      const int e = tid + 256 * i;
+      const int mm = AKC ? e / BK : e % BM;
+      const int kk = AKC ? e % BK : e / BM;
+      const int m = m0 + mm, k = k0 + kk;
+      ra[i] = (m < g.M && k < Kl && !(tri && k > m)) ? (T)s.A[(int64_t)m * s.sa0 + (int64_t)k * s.sa1] : T(0);
+    }
+#pragma unroll
+    for (int i = 0; i < EB; ++i) {
+      const int e = tid + 256 * i;
+      const int nn = BKC ? e / BK : e % BN;
+      const int kk = BKC ? e % BK : e / BN;
+      const int n = n0 + nn, k = k0 + kk;
+      rb[i] = (n < g.N && k < Kl) ? (T)s.B[(int64_t)n * s.sb0 + (int64_t)k * s.sb1] : T(0);
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < EA; ++i) {
+      const int e = tid + 256 * i;
+      const int mm = AKC ? e / BK : e % BM;
+      const int kk = AKC ? e % BK : e / BM;
+      As[buf][kk][mm] = ra[i];
+    }
+#pragma unroll
+    for (int i = 0; i < EB; ++i) {
+      const int e = tid + 256 * i;
+      const int nn = BKC ? e / BK : e % BN;
+      const int kk = BKC ? e % BK : e / BN;
+      Bs[buf][kk][nn] = rb[i];
+    }
+  };
+
+  if (T_ > 0) {
+    load(0);
+    store(0);
+  }
+  __syncthreads();
+  for (int t = 0; t < T_; ++t) {
+    const int buf = t & 1;
+    if (t + 1 < T_) load(t + 1);
+#pragma unroll
+    for (int k4 = 0; k4 < BK / 4; ++k4) {
+      T a[TM], b[TN];
+      const int kr = k4 * 4 + (lane >> 4);
+#pragma unroll
+      for (int i = 0; i < TM; ++i) a[i] = As[buf][kr][wm0 + i * 16 + (lane & 15)];
+#pragma unroll
+      for (int j = 0; j < TN; ++j) b[j] = Bs[buf][kr][wn0 + j * 16 + (lane & 15)];
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) acc[i][j] = Mfma16<T>::run(a[i], b[j], acc[i][j]);
+    }
+    if (t + 1 < T_) store(buf ^ 1);
+    __syncthreads();
+  }
+  FragCoord fc{m0 + wm0, n0 + wn0, lane, m0, n0, sizeof(T) == 8};
+  epi.template run<T, TM, TN>(acc, fc, reinterpret_cast<char*>(&As[0][0][0]));
+}
+
+// ---------------------------------------------------------------------------
+// BF16 MFMA engine (optionally 3-product split)
+// ---------------------------------------------------------------------------
+struct SegB {
+  const bf16_t *Ah, *Al;   // rows padded to BM multiple, ld multiple of BK
+  const bf16_t *Bh, *Bl;
+  int64_t lda, ldb;
+  int K;                   // multiple of BK (padded)
+};
+struct Bf16Args {
+  int nseg;
+  SegB seg[2];
+};
+
+template <int BM, int BN, int BK, bool X3, class Epi>
+__global__ __launch_bounds__(256) void gemm_bf16_kernel(Bf16Args g, Epi epi) {
+  constexpr int PAD = 8;
+  constexpr int LDS_ROW = BK + PAD;
+  constexpr int VA = BM * BK / 8 / 256;   // 16-byte vectors per thread
+  constexpr int VB = BN * BK / 8 / 256;
+  constexpr int TM = BM / 32, TN = BN / 32;
+  constexpr int NARR = X3 ? 2 : 1;
+  __shared__ bf16_t As[NARR][BM * LDS_ROW];
+  __shared__ bf16_t Bs[NARR][BN * LDS_ROW];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  const int wm0 = (wave >> 1) * (BM / 2), wn0 = (wave & 1) * (BN / 2);
+  const int t0 = g.seg[0].K / BK;
+  const int T_ = t0 + (g.nseg > 1 ? g.seg[1].K / BK : 0);
+
+  f4 acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[i][j] = f4{0, 0, 0, 0};
+
+  u4 ra[NARR][VA], rb[NARR][VB];
+  auto load = [&](int t) {
+    const SegB& s = (t < t0) ? g.seg[0] : g.seg[1];
+    const int k0 = (t < t0 ? t : t - t0) * BK;
+#pragma unroll
+    for (int i = 0; i < VA; ++i) {
+      const int e = tid + 256 * i;
+      const int mm = e / (BK / 8), kv = e % (BK / 8);
+      const int64_t off = (int64_t)(m0 + mm) * s.lda + k0 + kv * 8;
+      ra[0][i] = *reinterpret_cast<const u4*>(s.Ah + off);
+      if (X3) ra[NARR - 1][i] = *reinterpret_cast<const u4*>(s.Al + off);
+    }
+#pragma unroll
+    for (int i = 0; i < VB; ++i) {
+      const int e = tid + 256 * i;
+      const int nn = e / (BK / 8), kv = e % (BK / 8);
+      const int64_t off = (int64_t)(n0 + nn) * s.ldb + k0 + kv * 8;
+      rb[0][i] = *reinterpret_cast<const u4*>(s.Bh + off);
+      if (X3) rb[NARR - 1][i] = *reinterpret_cast<const u4*>(s.Bl + off);
+    }
+  };
+  auto store = [&]() {
+#pragma unroll
+    for (int h = 0; h < NARR; ++h) {
+#pragma unroll
+      for (int i = 0; i < VA; ++i) {
+        const int e = tid + 256 * i;
+        const int mm = e / (BK / 8), kv = e % (BK / 8);
+        *reinterpret_cast<u4*>(&As[h][mm * LDS_ROW + kv * 8]) = ra[h][i];
+      }
+#pragma unroll
+      for (int i = 0; i < VB; ++i) {
+        const int e = tid + 256 * i;
+        const int nn = e / (BK / 8), kv = e % (BK / 8);
+        *reinterpret_cast<u4*>(&Bs[h][nn * LDS_ROW + kv * 8]) = rb[h][i];
+      }
+    }
+  };
+
+  if (T_ > 0) {
+    load(0);
+    store();
+  }
+  __syncthreads();
+  for (int t = 0; t < T_; ++t) {
+    if (t + 1 < T_) load(t + 1);
+#pragma unroll
+    for (int kk = 0; kk < BK / 32; ++kk) {
+      const int ko = kk * 32 + 8 * (lane >> 4);
+      u4 ah[TM], bh[TN];
+      u4 al[X3 ? TM : 1], bl[X3 ? TN : 1];
+#pragma unroll
+      for (int i = 0; i < TM; ++i) {
+        const int r = wm0 + i * 16 + (lane & 15);
+        ah[i] = *reinterpret_cast<const u4*>(&As[0][r * LDS_ROW + ko]);
+        if (X3) al[i] = *reinterpret_cast<const u4*>(&As[NARR - 1][r * LDS_ROW + ko]);
+      }
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        const int r = wn0 + j * 16 + (lane & 15);
+        bh[j] = *reinterpret_cast<const u4*>(&Bs[0][r * LDS_ROW + ko]);
+        if (X3) bl[j] = *reinterpret_cast<const u4*>(&Bs[NARR - 1][r * LDS_ROW + ko]);
+      }
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+          if (X3) {
+            acc[i][j] = mfma_bf16(al[i], bh[j], acc[i][j]);
+            acc[i][j] = mfma_bf16(ah[i], bl[X3 ? j : 0], acc[i][j]);
+          }
+          acc[i][j] = mfma_bf16(ah[i], bh[j], acc[i][j]);
+        }
+    }
+    __syncthreads();
+    if (t + 1 < T_) {
+      store();
+      __syncthreads();
+    }
+  }
+  FragCoord fc{m0 + wm0, n0 + wn0, lane, m0, n0, false};
+  epi.template run<float, TM, TN>(acc, fc, reinterpret_cast<char*>(&As[0][0]));
+}
+
+// Shared LDS for epilogues that need it: the engines pass their operand LDS
+// after the final barrier of the K loop.
+
+// ---------------------------------------------------------------------------
+// Generic epilogue: C(m, n) = alpha * acc + beta * C(m, n) on a strided view.
+// ---------------------------------------------------------------------------
+template <typename CT> struct EpiAxpby {
+  CT* C;
+  int64_t scm, scn;
+  int M, N;
+  double alpha, beta;
+  template <typename T, int TM, int TN, class Acc>
+  __device__ void run(const Acc (&acc)[TM][TN], const FragCoord& f, char*) const {
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int j = 0; j < TN; ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int r = f.row(i, v), c = f.col(j);
+          if (r < M && c < N) {
+            CT* p = C + (int64_t)r * scm + (int64_t)c * scn;
+            const double val = alpha * (double)acc[i][j][v];
+            *p = (CT)(beta == 0.0 ? val : val + beta * (double)*p);
+          }
+        }
+  }
+};
+
+}  // namespace ffk

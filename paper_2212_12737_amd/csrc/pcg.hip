@@ -1,0 +1,241 @@
+// Preconditioned conjugate gradients for (K + lambda I) alpha = F (Eq. 1-2).
+//
+// Standard PCG (Hestenes-Stiefel recurrences) with alpha_0 = 0.  All vectors
+// and CG scalars are FP64 on the device; scalars never leave it except the two
+// needed for the stopping test and breakdown check (|r|^2 and p^T A p), read
+// back once per iteration.  The kernel product inside the iteration can run in
+// a reduced precision; then the true residual r = F - K_lambda alpha is
+// recomputed with the FP64 product every `refresh_every` iterations and
+// replaces the recursively updated one (residual replacement; p is kept), and
+// convergence is only declared on an FP64 true residual.  With `escalate`,
+// a refresh that shows divergence (10x the best true residual) or no
+// improvement for 30 refreshes moves the product one rung up the ladder
+// BF16 -> BF16X3 -> FP32 -> FP64 and restarts from the best iterate.
+// `flexible` switches beta to Polak-Ribiere, -gamma z^T q / rho.
+#include <chrono>
+
+#include "common.hpp"
+
+namespace ffk {
+
+enum { S_RHO0 = 0, S_RHO1 = 1, S_PAP = 2, S_RR = 3, S_ZQ = 4, S_FF = 5, S_TMP = 6, NSC = 8 };
+
+__global__ void k_axpy2(double* __restrict__ x, double* __restrict__ r, const double* __restrict__ p,
+                        const double* __restrict__ q, const double* __restrict__ sc, int rho, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double g = sc[rho] / sc[S_PAP];
+  x[i] += g * p[i];
+  r[i] -= g * q[i];
+}
+
+__global__ void k_update_p(double* __restrict__ p, const double* __restrict__ z, const double* __restrict__ sc,
+                           int rho_old, int rho_new, int flexible, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double beta;
+  if (flexible) {
+    const double g = sc[rho_old] / sc[S_PAP];
+    beta = -g * sc[S_ZQ] / sc[rho_old];
+  } else {
+    beta = sc[rho_new] / sc[rho_old];
+  }
+  p[i] = z[i] + beta * p[i];
+}
+
+__global__ void k_sub(const double* __restrict__ a, const double* __restrict__ b, double* __restrict__ c, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) c[i] = a[i] - b[i];
+}
+
+static int next_rung(int prec) {
+  switch (prec) {
+    case FFK_BF16: return FFK_BF16X3;
+    case FFK_BF16X3: return FFK_FP32;
+    default: return FFK_FP64;
+  }
+}
+
+struct Timer {
+  bool on;
+  hipStream_t st;
+  hipEvent_t a, b;
+  double* acc;
+  Timer(bool on_, hipStream_t s, double* acc_) : on(on_), st(s), acc(acc_) {
+    if (on) {
+      HIPCHK(hipEventCreate(&a));
+      HIPCHK(hipEventCreate(&b));
+      HIPCHK(hipEventRecord(a, st));
+    }
+  }
+  ~Timer() {
+    if (on) {
+      (void)hipEventRecord(b, st);
+      (void)hipEventSynchronize(b);
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, a, b);
+      *acc += ms;
+      (void)hipEventDestroy(a);
+      (void)hipEventDestroy(b);
+    }
+  }
+};
+
+ffk_status pcg_solve(ffk_system* s, const ffk_precond* P, const double* F, double* alpha, const ffk_pcg_opts* o,
+                     ffk_pcg_report* rep, hipStream_t st) {
+  const auto t_start = std::chrono::steady_clock::now();
+  const int64_t n = s->n;
+  const double lam = o->lambda;
+  require(lam > 0.0, "pcg_solve: lambda must be > 0");
+  require(o->tol > 0.0, "pcg_solve: tol must be > 0");
+  require(o->prec >= FFK_FP64 && o->prec <= FFK_BF16X3, "pcg_solve: unknown precision");
+  if (P) require(P->n == n, "pcg_solve: preconditioner size does not match the system");
+  const int64_t max_iter = o->max_iter > 0 ? o->max_iter : n;
+  const bool timing = o->timing != 0;
+  double t_mvm = 0, t_prec = 0, t_vec = 0, t_ref = 0;
+
+  DBuf r(n * 8), z(n * 8), p(n * 8), q(n * 8), tmp(n * 8), best(n * 8), sc(NSC * 8), part(kRedParts * 8);
+  double* R = r.as<double>();
+  double* Z = z.as<double>();
+  double* Pv = p.as<double>();
+  double* Q = q.as<double>();
+  double* SC = sc.as<double>();
+  double* PART = part.as<double>();
+  const int nb = cdiv(n, 256);
+  s->ctx->host_scratch.ensure(64);
+  double* hs = s->ctx->host_scratch.as<double>();
+
+  auto apply_prec = [&](const double* in, double* out) {
+    Timer tm(timing, st, &t_prec);
+    if (P) precond_apply(P, in, out, st);
+    else HIPCHK(hipMemcpyAsync(out, in, n * 8, hipMemcpyDeviceToDevice, st));
+  };
+  // r = F - K_lambda alpha (FP64); returns |r|^2
+  auto true_residual = [&]() -> double {
+    Timer tm(timing, st, &t_ref);
+    kernel_mvm(s, alpha, tmp.as<double>(), lam, FFK_FP64, st);
+    k_sub<<<nb, 256, 0, st>>>(F, tmp.as<double>(), R, n);
+    LAUNCHCHK();
+    dot64(R, R, n, PART, SC + S_RR, st);
+    HIPCHK(hipMemcpyAsync(hs, SC + S_RR, 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return hs[0];
+  };
+
+  dot64(F, F, n, PART, SC + S_FF, st);
+  HIPCHK(hipMemcpyAsync(hs, SC + S_FF, 8, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  const double fnorm = sqrt(hs[0]);
+  if (!std::isfinite(fnorm)) fail(FFK_ERR_NONFINITE, "pcg_solve: F contains NaN or Inf");
+
+  HIPCHK(hipMemsetAsync(alpha, 0, n * 8, st));
+  HIPCHK(hipMemcpyAsync(R, F, n * 8, hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipMemcpyAsync(best.get(), alpha, n * 8, hipMemcpyDeviceToDevice, st));
+  int prec = o->prec;
+  int rho = S_RHO0;
+  auto restart_direction = [&]() {
+    apply_prec(R, Z);
+    dot64(R, Z, n, PART, SC + rho, st);
+    HIPCHK(hipMemcpyAsync(Pv, Z, n * 8, hipMemcpyDeviceToDevice, st));
+  };
+  restart_direction();
+
+  ffk_status status = FFK_NOT_CONVERGED;
+  double best_true = fnorm * fnorm;   // alpha = 0
+  int64_t since_best = 0;
+  double rel_upd = 1.0, rel_true = 1.0;
+  int64_t it = 0, n_ref = 0, n_esc = 0;
+  if (fnorm == 0.0) {
+    status = FFK_OK;
+    rel_upd = rel_true = 0.0;
+  }
+  int64_t hist_len = 0;
+  const int refresh = o->refresh_every;
+  while (status == FFK_NOT_CONVERGED && it < max_iter) {
+    {
+      Timer tm(timing, st, &t_mvm);
+      kernel_mvm(s, Pv, Q, lam, prec, st);
+    }
+    {
+      Timer tm(timing, st, &t_vec);
+      dot64(Pv, Q, n, PART, SC + S_PAP, st);
+      k_axpy2<<<nb, 256, 0, st>>>(alpha, R, Pv, Q, SC, rho, n);
+      LAUNCHCHK();
+      dot64(R, R, n, PART, SC + S_RR, st);
+      HIPCHK(hipMemcpyAsync(hs, SC + S_PAP, 16, hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+    }
+    ++it;
+    const double pap = hs[0], rr = hs[1];
+    if (!(pap > 0.0) || !std::isfinite(pap) || !std::isfinite(rr)) {
+      status = FFK_ERR_BREAKDOWN;
+      break;
+    }
+    rel_upd = sqrt(rr) / fnorm;
+    if (rep && rep->hist_host && hist_len < rep->hist_cap) rep->hist_host[hist_len++] = rel_upd;
+    const bool candidate = rel_upd <= o->tol;
+    const bool periodic = refresh > 0 && (it % refresh) == 0 && prec != FFK_FP64;
+    if (candidate || periodic) {
+      const double tr = true_residual();
+      ++n_ref;
+      rel_true = sqrt(tr) / fnorm;
+      rel_upd = rel_true;
+      if (rel_true <= o->tol) {
+        status = FFK_OK;
+        break;
+      }
+      if (tr < best_true) {
+        best_true = tr;
+        since_best = 0;
+        HIPCHK(hipMemcpyAsync(best.get(), alpha, n * 8, hipMemcpyDeviceToDevice, st));
+      } else {
+        ++since_best;
+      }
+      if (o->escalate && prec != FFK_FP64 && (tr > 100.0 * best_true || since_best >= 30)) {
+        prec = next_rung(prec);
+        ++n_esc;
+        HIPCHK(hipMemcpyAsync(alpha, best.get(), n * 8, hipMemcpyDeviceToDevice, st));
+        true_residual();
+        since_best = 0;
+        restart_direction();
+        continue;
+      }
+    }
+    const int rho_new = rho ^ 1;
+    {
+      apply_prec(R, Z);
+      Timer tm(timing, st, &t_vec);
+      dot64(R, Z, n, PART, SC + rho_new, st);
+      if (o->flexible) dot64(Z, Q, n, PART, SC + S_ZQ, st);
+      k_update_p<<<nb, 256, 0, st>>>(Pv, Z, SC, rho, rho_new, o->flexible, n);
+      LAUNCHCHK();
+    }
+    rho = rho_new;
+  }
+  if (status == FFK_NOT_CONVERGED && it > 0) {
+    rel_true = sqrt(true_residual()) / fnorm;
+    ++n_ref;
+    if (rel_true <= o->tol) status = FFK_OK;
+  }
+  HIPCHK(hipStreamSynchronize(st));
+  const double total =
+      std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+  if (rep) {
+    rep->iters = it;
+    rep->n_refresh = n_ref;
+    rep->n_escalations = n_esc;
+    rep->rel_res_true = rel_true;
+    rep->rel_res_updated = rel_upd;
+    rep->final_prec = prec;
+    rep->status = status;
+    rep->t_mvm_ms = t_mvm;
+    rep->t_prec_ms = t_prec;
+    rep->t_vec_ms = t_vec;
+    rep->t_refresh_ms = t_ref;
+    rep->t_total_ms = total;
+    rep->hist_len = hist_len;
+  }
+  return status;
+}
+
+}  // namespace ffk

@@ -1,0 +1,290 @@
+"""GPU parity of the HIP path against the FP64 oracle, called through the C ABI.
+
+Tolerances: 1e-10 relative (norm-wise) for the FP64 operators; reduced
+precision MVMs as stated per test; solves judged on the oracle-computed true
+residual (several alpha satisfy |r| <= tol |F|, see the conditioning bound).
+"""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import kernel as ok
+from oracle import select as osel
+from oracle import solve as osv
+
+pytestmark = pytest.mark.gpu
+
+SIGMA = 10.0
+
+
+@pytest.fixture(scope="module")
+def ffk():
+    from paper_2212_12737_amd import ffk as m
+    m.lib()
+    return m
+
+
+@pytest.fixture(scope="module")
+def ctx(ffk):
+    return ffk.create(0)
+
+
+def dev(a, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def system(M, N, seed, sd=0.05, coulomb=True):
+    return synth.make_system(M, N, sd, coulomb, seed, seed + 1, seed + 2)
+
+
+def relerr(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+# ------------------------------------------------------------------ descriptor
+def test_descriptor_matches_oracle(ffk, ctx):
+    s = system(7, 300, 10)
+    S = ffk.descriptor_build(ctx, dev(s.R), SIGMA)
+    assert (S.N, S.M, S.D, S.n) == (300, 7, 21, 6300)
+    X = host(ffk.descriptor_export(ctx, S))
+    np.testing.assert_allclose(X, ok.descriptor(s.R), rtol=1e-14)
+
+
+def test_descriptor_rejects_coincident_atoms(ffk, ctx):
+    s = system(5, 4, 11)
+    R = s.R.copy()
+    R[2, 3] = R[2, 1]
+    with pytest.raises(ffk.FfkError):
+        ffk.descriptor_build(ctx, dev(R), SIGMA)
+
+
+# ------------------------------------------------------------ columns / diag
+def test_diag_and_columns_match_oracle(ffk, ctx):
+    s = system(6, 45, 12)
+    S = ffk.descriptor_build(ctx, dev(s.R), SIGMA)
+    d = host(ffk.kernel_diag(ctx, S))
+    np.testing.assert_allclose(d, ok.kernel_diag(s.R, SIGMA), rtol=1e-13)
+    cols = np.concatenate([[0, 1, 17, S.n - 1], np.random.default_rng(0).choice(S.n, 67, replace=False)])
+    C = host(ffk.kernel_columns(ctx, S, dev(cols, torch.int64)))
+    ref = ok.kernel_columns(s.R, cols, SIGMA)
+    assert np.abs(C - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+# ------------------------------------------------------------------------ MVM
+@pytest.mark.parametrize("M,N", [(7, 300), (21, 150), (9, 200), (4, 1), (3, 129), (12, 257)])
+def test_mvm_fp64_matches_oracle(ffk, ctx, M, N):
+    print("mvm fp64", M, N, flush=True)
+    s = system(M, N, 100 + M + N)
+    S = ffk.descriptor_build(ctx, dev(s.R), SIGMA)
+    v = synth.random_vectors(S.n, 7)
+    y = host(ffk.kernel_mvm(ctx, S, dev(v), shift=0.0, prec=ffk.FP64))
+    ref = ok.kernel_mvm(s.R, s.R, v, SIGMA)
+    assert relerr(y, ref) <= 1e-10
+    lam = 0.37
+    y2 = host(ffk.kernel_mvm(ctx, S, dev(v), shift=lam, prec=ffk.FP64))
+    assert relerr(y2, ref + lam * v) <= 1e-10
+
+
+def test_mvm_fp64_forces_label_vector(ffk, ctx):
+    """The product with the label vector (F is orthogonal to the rigid-motion null space)."""
+    s = synth.config_system(synth.CONFIGS["C1"])
+    S = ffk.descriptor_build(ctx, dev(s.R), SIGMA)
+    F = s.flat_forces()
+    y = host(ffk.kernel_mvm(ctx, S, dev(F)))
+    assert relerr(y, ok.kernel_mvm(s.R, s.R, F, SIGMA)) <= 1e-10
+
+
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-6), ("bf16x3", 1e-6), ("bf16", 3e-3)])
+@pytest.mark.parametrize("M,N", [(7, 300), (21, 150)])
+def test_mvm_reduced_precision(ffk, ctx, prec, tol, M, N):
+    print("mvm", prec, M, N, flush=True)
+    s = system(M, N, 200 + M + N, sd=0.08)
+    S = ffk.descriptor_build(ctx, dev(s.R), SIGMA)
+    v = synth.random_vectors(S.n, 8)
+    y = host(ffk.kernel_mvm(ctx, S, dev(v), prec=ffk.PRECISIONS[prec]))
+    ref = ok.kernel_mvm(s.R, s.R, v, SIGMA)
+    err = relerr(y, ref)
+    print("relerr", prec, err, flush=True)
+    assert err <= tol
+
+
+def test_predict_matches_oracle(ffk, ctx):
+    tr = synth.make_system(8, 170, 0.05, True, 31, 32, 33)
+    te = synth.make_system(8, 37, 0.05, True, 31, 34, 33)
+    Str = ffk.descriptor_build(ctx, dev(tr.R), SIGMA)
+    Ste = ffk.descriptor_build(ctx, dev(te.R), SIGMA)
+    alpha = synth.random_vectors(Str.n, 3)
+    Fp = host(ffk.kernel_predict(ctx, Str, Ste, dev(alpha)))
+    ref = ok.kernel_mvm(te.R, tr.R, alpha, SIGMA)
+    assert relerr(Fp, ref) <= 1e-10
+
+
+# ------------------------------------------------------------------ selection
+@pytest.mark.parametrize("M,N,k", [(9, 200, 100), (7, 300, 700), (5, 3, 45)])
+def test_uniform_selection_bit_exact(ffk, ctx, M, N, k):
+    s = system(M, N, 300 + N)
+    S = ffk.descriptor_build(ctx, dev(s.R), SIGMA)
+    for seed in (0, 3003, 2 ** 63 + 5):
+        idx = host(ffk.nystrom_select(ctx, S, "uniform", k, seed=seed))
+        assert idx.tolist() == osel.select_uniform(S.n, k, seed).tolist()
+
+
+def test_score_sampling_bit_exact(ffk, ctx):
+    s = system(6, 400, 301)
+    S = ffk.descriptor_build(ctx, dev(s.R), SIGMA)
+    g = synth.random_weights(S.N, 17, 0.05, 3.0)
+    k = 333
+    idx = host(ffk.nystrom_select(ctx, S, "scores", k, seed=99, weights=dev(g)))
+    ref = osel.select_weighted(osel.score_weights(g, S.M), k, 99, osel.STREAM_SCORES)
+    if idx.tolist() != ref.tolist():
+        # only a near-tie of two keys (one ulp of log) may reorder them
+        keys = osel.weighted_keys(osel.score_weights(g, S.M), 99, osel.STREAM_SCORES)
+        diff = set(idx.tolist()) ^ set(ref.tolist())
+        thr = np.sort(keys)[::-1][k - 1]
+        assert all(abs(keys[i] - thr) <= 1e-13 * abs(thr) for i in diff)
+
+
+def test_pivoted_cholesky_sequence(ffk, ctx):
+    s = system(6, 20, 302)
+    S = ffk.descriptor_build(ctx, dev(s.R), SIGMA)
+    K = ok.dense_kernel(s.R, SIGMA)
+    k = 90
+    gp = host(ffk.nystrom_select(ctx, S, "pivchol", k))
+    L, piv, keff, d = osel.incomplete_cholesky(lambda i: K[:, i], np.diag(K), k)
+    assert len(gp) == keff
+    # identical until the first near-tie (top-2 remaining diagonals within 1e-9)
+    dd = np.diag(K).copy()
+    Lm = np.zeros((K.shape[0], 0))
+    for m in range(keff):
+        if gp[m] != piv[m]:
+            res = np.diag(K) - (Lm ** 2).sum(1)
+            res[piv[:m]] = -np.inf
+            top = np.sort(res)[::-1]
+            assert top[0] - top[1] <= 1e-9 * top[0], (m, gp[m], piv[m])
+            break
+        Lm = L[:, :m + 1]
+
+
+def test_pivoted_cholesky_stops_at_numerical_rank(ffk, ctx):
+    s = system(5, 6, 303)
+    S = ffk.descriptor_build(ctx, dev(s.R), SIGMA)
+    gp = host(ffk.nystrom_select(ctx, S, "pivchol", S.n))
+    assert len(gp) <= S.n - 6 * S.N
+    assert len(set(gp.tolist())) == len(gp)
+
+
+# ------------------------------------------------------------- preconditioner
+def test_precond_factor_and_apply_match_oracle(ffk, ctx):
+    s = system(6, 30, 304)
+    S = ffk.descriptor_build(ctx, dev(s.R), SIGMA)
+    K = ok.dense_kernel(s.R, SIGMA)
+    idx = osel.select_uniform(S.n, 150, 7)            # > 2 panels, ragged
+    P = ffk.precond_build(ctx, S, dev(idx, torch.int64), 1e-4, store=ffk.FP64)
+    L = host(ffk.precond_export(ctx, P, S.n))
+    Lo, piv, keff, _ = osel.incomplete_cholesky(lambda i: K[:, i], np.diag(K), len(idx), order=idx)
+    assert P.k_eff == keff
+    Lo = Lo[:, [j for j in range(len(idx)) if np.any(Lo[:, j] != 0)]]
+    assert np.abs(L @ L.T - Lo @ Lo.T).max() <= 1e-10 * np.abs(K).max()
+    r = synth.random_vectors(S.n, 5)
+    z = host(ffk.precond_apply(ctx, P, dev(r)))
+    zo = osv.woodbury(Lo, 1e-4)(r)
+    assert relerr(z, zo) <= 1e-9
+    # FP32 storage: still an SPD operator; close to the FP64 one
+    P32 = ffk.precond_build(ctx, S, dev(idx, torch.int64), 1e-4, store=ffk.FP32)
+    z32 = host(ffk.precond_apply(ctx, P32, dev(r)))
+    assert relerr(z32, zo) <= 1e-3
+    assert float(r @ z32) > 0
+
+
+def test_precond_drops_dependent_columns(ffk, ctx):
+    s = system(5, 8, 305)
+    S = ffk.descriptor_build(ctx, dev(s.R), SIGMA)
+    m3 = 3 * S.M
+    idx = np.concatenate([np.arange(m3), [3, m3 + 2]])     # a whole geometry (rank 3M-6) + a duplicate
+    P = ffk.precond_build(ctx, S, dev(idx, torch.int64), 1e-6)
+    assert P.dropped and P.k_eff == m3 - 6 + 1
+
+
+def test_leverage_estimate_matches_oracle(ffk, ctx):
+    s = system(6, 30, 306)
+    S = ffk.descriptor_build(ctx, dev(s.R), SIGMA)
+    lam, k, pilot, seed = 1e-5, 60, 80, 4
+    idx, tau = ffk.nystrom_select(ctx, S, "leverage", k, lam=lam, seed=seed, pilot=pilot, return_tau=True)
+    S0 = osel.select_uniform(S.n, pilot, seed, osel.STREAM_PILOT)
+    C = ok.kernel_columns(s.R, S0, SIGMA)
+    tau_o = osel.leverage_estimate(C, ok.kernel_diag(s.R, SIGMA), S0, lam)
+    assert np.abs(host(tau) - tau_o).max() <= 1e-6
+    ref = osel.select_weighted(tau_o, k, seed, osel.STREAM_LEVERAGE)
+    assert len(set(host(idx).tolist()) & set(ref.tolist())) >= k - 2
+
+
+def test_exact_rls_matches_oracle(ffk, ctx):
+    s = system(6, 20, 307)
+    S = ffk.descriptor_build(ctx, dev(s.R), SIGMA)
+    lam = 1e-6
+    tau = host(ffk.exact_rls(ctx, S, lam))
+    K = ok.dense_kernel(s.R, SIGMA)
+    ref = osel.exact_ridge_leverage(K, lam)
+    assert np.abs(tau - ref).max() <= 1e-7
+
+
+# ------------------------------------------------------------------------ PCG
+def test_plain_cg_matches_cholesky(ffk, ctx):
+    s = system(5, 12, 308)
+    S = ffk.descriptor_build(ctx, dev(s.R), SIGMA)
+    K = ok.dense_kernel(s.R, SIGMA)
+    lam = np.linalg.eigvalsh(K).max() / 1e3
+    F = s.flat_forces()
+    a, rep = ffk.pcg_solve(ctx, S, None, dev(F), lam, tol=1e-13, max_iter=2000)
+    ref = osv.cholesky_solve(K, lam, F)
+    assert rep.status == 0
+    assert relerr(host(a), ref) <= 1e-10
+
+
+@pytest.fixture(scope="module")
+def c1(ffk, ctx):
+    cfg = synth.CONFIGS["C1"]
+    s = synth.config_system(cfg)
+    S = ffk.descriptor_build(ctx, dev(s.R), cfg.sigma)
+    K = ok.dense_kernel(s.R, cfg.sigma)
+    idx = ffk.nystrom_select(ctx, S, "uniform", cfg.k, seed=cfg.sel_seed)
+    return cfg, s, S, K, idx
+
+
+def oracle_relres(K, lam, a, F):
+    return np.linalg.norm(K @ a + lam * a - F) / np.linalg.norm(F)
+
+
+def test_pcg_c1_fp64_uniform(ffk, ctx, c1):
+    cfg, s, S, K, idx = c1
+    assert host(idx).tolist() == osel.select_uniform(S.n, cfg.k, cfg.sel_seed).tolist()
+    P = ffk.precond_build(ctx, S, idx, cfg.lam)
+    F = s.flat_forces()
+    a, rep = ffk.pcg_solve(ctx, S, P, dev(F), cfg.lam, tol=1e-6, prec=ffk.FP64)
+    print("C1 fp64 iters", rep.iters, rep.rel_res_true, flush=True)
+    assert rep.status == 0
+    assert oracle_relres(K, cfg.lam, host(a), F) <= 1.01e-6
+    ref = osv.cholesky_solve(K, cfg.lam, F)
+    assert np.linalg.norm(K @ host(a) - K @ ref) <= 2.1e-6 * np.linalg.norm(F)
+    # same iteration count as the oracle's textbook PCG up to rounding effects
+    L, _, _, _ = osel.incomplete_cholesky(lambda i: K[:, i], np.diag(K), cfg.k, order=host(idx))
+    _, it_o, _ = osv.pcg(lambda v: K @ v + cfg.lam * v, F, osv.woodbury(L, cfg.lam), tol=1e-6)
+    assert abs(rep.iters - it_o) <= 0.05 * it_o
+
+
+@pytest.mark.parametrize("prec", ["bf16x3", "fp32", "bf16"])
+def test_pcg_c1_mixed_precision_reaches_fp64_residual(ffk, ctx, c1, prec):
+    cfg, s, S, K, idx = c1
+    P = ffk.precond_build(ctx, S, idx, cfg.lam, store=ffk.FP32)
+    F = s.flat_forces()
+    a, rep = ffk.pcg_solve(ctx, S, P, dev(F), cfg.lam, tol=1e-6, prec=ffk.PRECISIONS[prec], refresh_every=10,
+                           escalate=True, max_iter=20000)
+    print("C1", prec, "iters", rep.iters, "esc", rep.n_escalations, "final", rep.final_prec, rep.rel_res_true,
+          flush=True)
+    assert rep.status == 0
+    assert oracle_relres(K, cfg.lam, host(a), F) <= 1.01e-6
