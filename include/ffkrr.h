@@ -179,6 +179,8 @@ typedef struct {
                              refresh shows no progress (BF16 -> BF16X3 -> FP32 -> FP64) */
   int32_t flexible;       /* 1: Polak-Ribiere beta (robust to inexact operators) */
   int32_t timing;         /* 1: time MVM / preconditioner / vector phases with events */
+  double switch_below;    /* > 0: FP64 products while the updated residual is above
+                             switch_below |F|, then `prec` (0: `prec` from the start) */
 } ffk_pcg_opts;
 
 typedef struct {
@@ -189,6 +191,8 @@ typedef struct {
   double rel_res_updated; /* final recursively updated residual / |F| */
   int32_t final_prec;     /* precision in use at the end */
   int32_t status;         /* same as the return value */
+  int64_t switch_iter;    /* iteration at which the products left FP64 (-1: never) */
+  int64_t esc_iter[3];    /* iterations at which escalations happened (-1: none) */
   double t_mvm_ms, t_prec_ms, t_vec_ms, t_refresh_ms, t_total_ms;
   double* hist_host;      /* optional caller buffer: updated residual norm / |F| per iteration */
   int64_t hist_cap;       /* capacity of hist_host */

@@ -156,6 +156,7 @@ struct MvmWork {
   DBuf Wnh, Wnl;       // N x N bf16
   DBuf wpart;          // N x tilesN double (row-sum partials of W)
   DBuf G;              // N x D double
+  DBuf part;           // split-K partials of GEMM 2
 };
 
 }  // namespace ffk
@@ -186,12 +187,14 @@ struct ffk_system {
 struct ffk_precond {
   ffk_ctx* ctx = nullptr;
   int64_t n = 0, k = 0, k_eff = 0;
+  int64_t ld = 0, ldf = 0;  // leading dimensions of L and Finv (multiples of 64)
   double lambda = 0.0;
   int32_t store = FFK_FP64;
   ffk::DBuf L;              // n x k column-major (double or float)
   ffk::DBuf Finv;           // k x k row-major lower-triangular inverse of chol(core)
   ffk::DBuf FinvT;          // its transpose, row-major
   ffk::DBuf y, t1, t;       // k-vectors
+  ffk::DBuf work;           // partial sums of the split GEMVs
   int64_t bytes = 0;
 };
 
@@ -257,8 +260,9 @@ void leverage_estimate(ffk_system* sys, const int64_t* pilot, int64_t s, double 
 
 // precond.hip
 // Incomplete Cholesky with pivots forced to idx (order kept) of K + shift I.
-// L: n x k column-major double.  kept (host, k) receives which columns survived.
-int64_t icd_forced(ffk_system* sys, const int64_t* idx, int64_t k, double shift, double* L,
+// L: n x k column-major double with leading dimension ld (>= n, zero padded).
+// kept (host, k) receives which columns survived.
+int64_t icd_forced(ffk_system* sys, const int64_t* idx, int64_t k, double shift, double* L, int64_t ld,
                    std::vector<char>* kept, hipStream_t st);
 ffk_precond* precond_build(ffk_system* sys, const int64_t* idx, int64_t k, double lambda,
                            int store, bool* dropped, hipStream_t st);

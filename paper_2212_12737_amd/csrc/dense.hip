@@ -98,38 +98,36 @@ __global__ __launch_bounds__(256) void k_potf2(double* A, int jb, int64_t lda, i
   }
 }
 
-// Rows below a factored diagonal block: A[i, j0:j0+jb] <- A[i, j0:j0+jb] L_jj^{-T}.
-__global__ __launch_bounds__(256) void k_trsm_rows(double* A, int64_t n, int64_t lda, int64_t j0, int jb) {
+// Inverse of the jb x jb lower-triangular block at A (lda) into X (NB x NB row-major, zero padded).
+__global__ __launch_bounds__(64) void k_tri_inverse(const double* A, int jb, int64_t lda, double* X) {
   __shared__ double L[NB][NB + 1];
   const int tid = threadIdx.x;
-  for (int e = tid; e < jb * jb; e += 256) {
-    const int r = e % jb, c = e / jb;
-    L[r][c] = A[(j0 + r) + (j0 + c) * lda];
+  for (int e = tid; e < NB * NB; e += 64) {
+    const int r = e % NB, c = e / NB;
+    L[r][c] = (r < jb && c < jb) ? A[r + c * lda] : (r == c ? 1.0 : 0.0);
   }
   __syncthreads();
-  const int64_t i = j0 + jb + (int64_t)blockIdx.x * 256 + tid;
-  if (i >= n) return;
+  const int c = tid;
   double x[NB];
 #pragma unroll
-  for (int c = 0; c < NB; ++c)
-    if (c < jb) x[c] = A[i + (j0 + c) * lda];
+  for (int r = 0; r < NB; ++r) x[r] = 0.0;
+  // column c of the inverse, computed in registers with static indices
 #pragma unroll
-  for (int c = 0; c < NB; ++c) {
-    if (c < jb) {
-      double v = x[c];
+  for (int r = 0; r < NB; ++r) {
+    if (r == c) x[r] = 1.0 / L[r][r];
+    if (r > c) {
+      double sacc = 0.0;
 #pragma unroll
-      for (int q = 0; q < NB; ++q)
-        if (q < c) v -= x[q] * L[c][q];
-      x[c] = v / L[c][c];
+      for (int q = 0; q < r; ++q) sacc += L[r][q] * x[q];
+      x[r] = -sacc / L[r][r];
     }
   }
 #pragma unroll
-  for (int c = 0; c < NB; ++c)
-    if (c < jb) A[i + (j0 + c) * lda] = x[c];
+  for (int r = 0; r < NB; ++r) X[r * NB + c] = x[r];
 }
 
 int64_t potrf_lower(double* A, int64_t n, int64_t lda, hipStream_t st) {
-  DBuf info(8);
+  DBuf info(8), Xinv(NB * NB * 8);
   const unsigned long long none = ~0ull;
   HIPCHK(hipMemcpyAsync(info.get(), &none, 8, hipMemcpyHostToDevice, st));
   for (int64_t j0 = 0; j0 < n; j0 += NB) {
@@ -138,9 +136,11 @@ int64_t potrf_lower(double* A, int64_t n, int64_t lda, hipStream_t st) {
     LAUNCHCHK();
     const int64_t rest = n - j0 - jb;
     if (rest > 0) {
-      k_trsm_rows<<<cdiv(rest, 256), 256, 0, st>>>(A, n, lda, j0, jb);
+      // panel <- panel L_jj^-T  (in place: one 128-row tile covers all jb columns)
+      k_tri_inverse<<<1, 64, 0, st>>>(A + j0 + j0 * lda, jb, lda, Xinv.as<double>());
       LAUNCHCHK();
       double* P = A + (j0 + jb) + j0 * lda;
+      gemm64((int)rest, jb, jb, 1.0, View64{P, 1, lda}, View64{Xinv.as<double>(), NB, 1}, 0.0, P, 1, lda, false, st);
       double* C = A + (j0 + jb) + (j0 + jb) * lda;
       gemm64((int)rest, (int)rest, jb, -1.0, View64{P, 1, lda}, View64{P, 1, lda}, 1.0, C, 1, lda, true, st);
     }

@@ -152,14 +152,17 @@ __global__ __launch_bounds__(256) void gemm_scalar_kernel(ScalarArgs<TI> g, Epi 
     }
   };
 
-  if (T_ > 0) {
-    load(0);
+  // split-K: block z of gridDim.z takes a contiguous range of the tiles
+  const int tb = (int)((int64_t)T_ * blockIdx.z / gridDim.z);
+  const int te = (int)((int64_t)T_ * (blockIdx.z + 1) / gridDim.z);
+  if (te > tb) {
+    load(tb);
     store(0);
   }
   __syncthreads();
-  for (int t = 0; t < T_; ++t) {
-    const int buf = t & 1;
-    if (t + 1 < T_) load(t + 1);
+  for (int t = tb; t < te; ++t) {
+    const int buf = (t - tb) & 1;
+    if (t + 1 < te) load(t + 1);
 #pragma unroll
     for (int k4 = 0; k4 < BK / 4; ++k4) {
       T a[TM], b[TN];
@@ -173,7 +176,7 @@ __global__ __launch_bounds__(256) void gemm_scalar_kernel(ScalarArgs<TI> g, Epi 
 #pragma unroll
         for (int j = 0; j < TN; ++j) acc[i][j] = Mfma16<T>::run(a[i], b[j], acc[i][j]);
     }
-    if (t + 1 < T_) store(buf ^ 1);
+    if (t + 1 < te) store(buf ^ 1);
     __syncthreads();
   }
   FragCoord fc{m0 + wm0, n0 + wn0, lane, m0, n0, sizeof(T) == 8};
@@ -256,13 +259,15 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(Bf16Args g, Epi epi) {
     }
   };
 
-  if (T_ > 0) {
-    load(0);
+  const int tb = (int)((int64_t)T_ * blockIdx.z / gridDim.z);
+  const int te = (int)((int64_t)T_ * (blockIdx.z + 1) / gridDim.z);
+  if (te > tb) {
+    load(tb);
     store();
   }
   __syncthreads();
-  for (int t = 0; t < T_; ++t) {
-    if (t + 1 < T_) load(t + 1);
+  for (int t = tb; t < te; ++t) {
+    if (t + 1 < te) load(t + 1);
 #pragma unroll
     for (int kk = 0; kk < BK / 32; ++kk) {
       const int ko = kk * 32 + 8 * (lane >> 4);
@@ -292,7 +297,7 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(Bf16Args g, Epi epi) {
         }
     }
     __syncthreads();
-    if (t + 1 < T_) {
+    if (t + 1 < te) {
       store();
       __syncthreads();
     }
@@ -329,5 +334,33 @@ template <typename CT> struct EpiAxpby {
         }
   }
 };
+
+// Split-K partial store: part[(z * rows + r) * ldp + c] = acc for r < rows, c < cols.
+template <typename PT> struct EpiPart {
+  PT* part;
+  int64_t ldp;
+  int rows, cols;
+  template <typename T, int TM, int TN, class Acc>
+  __device__ void run(const Acc (&acc)[TM][TN], const FragCoord& f, char*) const {
+    PT* base = part + (int64_t)blockIdx.z * rows * ldp;
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int j = 0; j < TN; ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int r = f.row(i, v), c = f.col(j);
+          if (r < rows && c < cols) base[(int64_t)r * ldp + c] = (PT)acc[i][j][v];
+        }
+  }
+};
+
+// Number of K splits that brings a GEMM with `tiles` output tiles to >= 512
+// workgroups while keeping at least two K tiles per split.
+inline int pick_splits(int64_t tiles, int64_t ktiles) {
+  int s = 1;
+  while (tiles * s < 512 && (int64_t)s * 4 <= ktiles) s *= 2;
+  return s;
+}
 
 }  // namespace ffk

@@ -16,78 +16,113 @@ namespace ffk {
 
 static int64_t rup(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
 
-// u_j = J_j v_j for one geometry per block; also pd_j = x_c,j . u_j and
-// optional reduced-precision copies of U.
-template <bool W32, bool WBF>
-__global__ void k_jv(const double* __restrict__ R, const int* __restrict__ pairs,
-                     const double* __restrict__ v, const double* __restrict__ Xc, int M, int64_t D,
-                     double* __restrict__ U64, double* __restrict__ pd, float* __restrict__ U32,
-                     bf16_t* __restrict__ Uh, bf16_t* __restrict__ Ul, int64_t ldu) {
+// u_g = J_g v_g for a group of GT geometries per block (threads run over the
+// descriptor pairs, so every global access is coalesced); also
+// pd_g = x_c,g . u_g, the per-block column partial sums of U, and the copies of
+// U the chosen precision needs (FP64, FP32, or split BF16 in both layouts).
+constexpr int GT = 16;
+
+template <bool W64, bool W32, bool WBF>
+__global__ __launch_bounds__(256) void k_jv_tile(const double* __restrict__ R, const int* __restrict__ pairs,
+                                                 const double* __restrict__ v, const double* __restrict__ Xc,
+                                                 int64_t N, int M, int64_t D, double* __restrict__ U64,
+                                                 float* __restrict__ U32, bf16_t* __restrict__ Uh,
+                                                 bf16_t* __restrict__ Ul, int64_t ldu, bf16_t* __restrict__ UTh,
+                                                 bf16_t* __restrict__ UTl, int64_t ldut, double* __restrict__ pd,
+                                                 double* __restrict__ cpart) {
   extern __shared__ double sm[];
-  double* sR = sm;
-  double* sv = sm + 3 * M;
-  __shared__ double red[256];
-  const int64_t g = blockIdx.x;
-  for (int i = threadIdx.x; i < 3 * M; i += blockDim.x) {
-    sR[i] = R[g * 3 * M + i];
-    sv[i] = v[g * 3 * M + i];
+  const int m3 = 3 * M;
+  double* sR = sm;              // GT x 3M
+  double* sv = sm + GT * m3;    // GT x 3M
+  __shared__ double red[GT][4];
+  const int64_t g0 = (int64_t)blockIdx.x * GT;
+  const int ng = (int)(N - g0 < GT ? N - g0 : GT);
+  for (int e = threadIdx.x; e < ng * m3; e += blockDim.x) {
+    sR[e] = R[g0 * m3 + e];
+    sv[e] = v[g0 * m3 + e];
   }
   __syncthreads();
-  double acc = 0.0;
+  double pdp[GT];
+#pragma unroll
+  for (int gl = 0; gl < GT; ++gl) pdp[gl] = 0.0;
   for (int64_t d = threadIdx.x; d < D; d += blockDim.x) {
     const int pq = pairs[d];
     const int p = 3 * (pq >> 16), q = 3 * (pq & 0xFFFF);
-    const double dx = sR[p] - sR[q], dy = sR[p + 1] - sR[q + 1], dz = sR[p + 2] - sR[q + 2];
-    const double ir = 1.0 / sqrt(dx * dx + dy * dy + dz * dz);
-    const double ir3 = ir * ir * ir;
-    const double u = -(dx * (sv[p] - sv[q]) + dy * (sv[p + 1] - sv[q + 1]) + dz * (sv[p + 2] - sv[q + 2])) * ir3;
-    U64[g * D + d] = u;
-    acc += u * Xc[g * D + d];
-    if (W32) U32[g * D + d] = (float)u;
-    if (WBF) {
-      const float uf = (float)u;
-      const bf16_t h = f2bf(uf);
-      Uh[g * ldu + d] = h;
-      Ul[g * ldu + d] = f2bf(uf - bf2f(h));
+    double cs = 0.0;
+    float uf[GT];
+#pragma unroll
+    for (int gl = 0; gl < GT; ++gl) {
+      double u = 0.0;
+      if (gl < ng) {
+        const double* Rg = sR + gl * m3;
+        const double* vg = sv + gl * m3;
+        const double dx = Rg[p] - Rg[q], dy = Rg[p + 1] - Rg[q + 1], dz = Rg[p + 2] - Rg[q + 2];
+        const double ir = 1.0 / sqrt(dx * dx + dy * dy + dz * dz);
+        u = -(dx * (vg[p] - vg[q]) + dy * (vg[p + 1] - vg[q + 1]) + dz * (vg[p + 2] - vg[q + 2])) * (ir * ir * ir);
+        const int64_t o = (g0 + gl) * D + d;
+        pdp[gl] += u * Xc[o];
+        if (W64) U64[o] = u;
+        if (W32) U32[o] = (float)u;
+        if (WBF) {
+          const float f = (float)u;
+          const bf16_t h = f2bf(f);
+          Uh[(g0 + gl) * ldu + d] = h;
+          Ul[(g0 + gl) * ldu + d] = f2bf(f - bf2f(h));
+        }
+      }
+      cs += u;
+      uf[gl] = (float)u;
+    }
+    cpart[(int64_t)blockIdx.x * D + d] = cs;
+    if (WBF) {   // transposed copy: 16 consecutive geometries of row d
+      bf16_t hh[GT], ll[GT];
+#pragma unroll
+      for (int gl = 0; gl < GT; ++gl) {
+        hh[gl] = f2bf(uf[gl]);
+        ll[gl] = f2bf(uf[gl] - bf2f(hh[gl]));
+      }
+#pragma unroll
+      for (int gl = 0; gl < GT; ++gl)
+        if (gl < ng) {
+          UTh[d * ldut + g0 + gl] = hh[gl];
+          UTl[d * ldut + g0 + gl] = ll[gl];
+        }
     }
   }
-  red[threadIdx.x] = acc;
-  __syncthreads();
-  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
-    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
-    __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int gl = 0; gl < GT; ++gl) {
+    double x = pdp[gl];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+    if (lane == 0) red[gl][wave] = x;
   }
-  if (threadIdx.x == 0) pd[g] = red[0];
+  __syncthreads();
+  if (threadIdx.x < ng) {
+    const int gl = threadIdx.x;
+    pd[g0 + gl] = (red[gl][0] + red[gl][1]) + (red[gl][2] + red[gl][3]);
+  }
 }
 
-// Column sums of an N x D matrix in two deterministic stages.
-__global__ void k_colsum_part(const double* __restrict__ U, int64_t N, int64_t D, double* __restrict__ part) {
+// s = sum of the per-block column partials (nblk x D): 64 columns x 4 row
+// groups per block, combined in a fixed order.
+__global__ __launch_bounds__(256) void k_colsum_final(const double* __restrict__ part, int nblk, int64_t D,
+                                                      double* __restrict__ s) {
   __shared__ double sh[4][64];
   const int c = threadIdx.x & 63, rg = threadIdx.x >> 6;
   const int64_t col = (int64_t)blockIdx.x * 64 + c;
-  const int64_t r0 = (int64_t)blockIdx.y * 256;
-  double s = 0.0;
-  if (col < D)
-    for (int r = rg; r < 256 && r0 + r < N; r += 4) s += U[(r0 + r) * D + col];
-  sh[rg][c] = s;
+  double a0 = 0.0, a1 = 0.0;
+  if (col < D) {
+    int i = rg;
+    for (; i + 4 < nblk; i += 8) {
+      a0 += part[(int64_t)i * D + col];
+      a1 += part[(int64_t)(i + 4) * D + col];
+    }
+    if (i < nblk) a0 += part[(int64_t)i * D + col];
+  }
+  sh[rg][c] = a0 + a1;
   __syncthreads();
-  if (rg == 0 && col < D) part[(int64_t)blockIdx.y * D + col] = (sh[0][c] + sh[1][c]) + (sh[2][c] + sh[3][c]);
-}
-__global__ void k_colsum_final(const double* __restrict__ part, int nchunk, int64_t D, double scale,
-                               double* __restrict__ s) {
-  const int64_t col = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (col >= D) return;
-  double a = 0.0;
-  for (int i = 0; i < nchunk; ++i) a += part[(int64_t)i * D + col];
-  s[col] = a * scale;
-}
-
-void colsum(const double* U, int64_t N, int64_t D, double* part, double* s, double scale, hipStream_t st) {
-  const int nchunk = cdiv(N, 256);
-  k_colsum_part<<<dim3(cdiv(D, 64), nchunk), 256, 0, st>>>(U, N, D, part);
-  LAUNCHCHK();
-  k_colsum_final<<<cdiv(D, 256), 256, 0, st>>>(part, nchunk, D, scale, s);
-  LAUNCHCHK();
+  if (rg == 0 && col < D) s[col] = (sh[0][c] + sh[1][c]) + (sh[2][c] + sh[3][c]);
 }
 
 // y_g = J_g^T G_g + shift v_g, one geometry per block (thread per atom).
@@ -271,48 +306,87 @@ struct EpiCoeffRect {
   }
 };
 
-// ---------------------------------------------------------------- driver ----
+// Split-K reduction for GEMM 2: G = sum_z part_z + a0 s_c + w_r Xt_r,c (one block per row).
+template <typename PT>
+__global__ __launch_bounds__(256) void k_g_reduce(const PT* __restrict__ part, int splits, int64_t rows, int64_t cols,
+                                                  const double* __restrict__ s, const double* __restrict__ Xt,
+                                                  const double* __restrict__ wpart, int ntn, double a0,
+                                                  double* __restrict__ G) {
+  __shared__ double wsh;
+  const int64_t r = blockIdx.x;
+  if (threadIdx.x == 0) {
+    double w = 0.0;
+    for (int q = 0; q < ntn; ++q) w += wpart[r * ntn + q];
+    wsh = w;
+  }
+  __syncthreads();
+  const double w = wsh;
+  for (int64_t c = threadIdx.x; c < cols; c += blockDim.x) {
+    double acc = 0.0;
+    for (int z = 0; z < splits; ++z) acc += (double)part[((int64_t)z * rows + r) * cols + c];
+    G[r * cols + c] = acc + a0 * s[c] + w * Xt[r * cols + c];
+  }
+}
+
 static inline void mark(hipEvent_t* ev, int i, hipStream_t st) {
   if (ev) HIPCHK(hipEventRecord(ev[i], st));
 }
 
+// Shared operands of one product: target descriptor (rows of GEMM 1/2) and
+// source quantities.
+struct MvmArgs {
+  int64_t Nt, Ns, D;
+  double a0;
+  const double* Xt64;    // target X_c (FP64, Nt x D), for the diag(w) X term
+  const double* pd;      // Ns
+  const double* s;       // D
+  double* wpart;         // Nt x ntn
+  double* G;             // Nt x D
+  void* part;            // split-K partials
+  size_t part_bytes;
+};
+
 template <typename T>
-static void mvm_scalar(ffk_system* s, int prec, const double* pd, const double* sv, hipStream_t st,
-                       hipEvent_t* ev) {
-  const int N = (int)s->N;
-  const int64_t D = s->D;
-  MvmWork& w = s->work;
-  CoeffSet& cs = s->coef[prec];
-  const T* Xc = prec == FFK_FP64 ? (const T*)s->Xc.get() : (const T*)s->Xc32.get();
-  const T* U = prec == FFK_FP64 ? (const T*)w.U64.get() : (const T*)w.U32.get();
-  T* Wn = prec == FFK_FP64 ? (T*)w.Wn64.get() : (T*)w.Wn32.get();
-  const int ntn = cdiv(N, 128);
+static void mvm_gemms_scalar(const MvmArgs& a, const T* Xt, const T* Xs, const T* U, const T* dA, const T* Bc, T* Wn,
+                             hipStream_t st, hipEvent_t* ev) {
+  const int Nt = (int)a.Nt, Ns = (int)a.Ns;
+  const int64_t D = a.D;
+  const int ntn = cdiv(Ns, 128);
   {
     ScalarArgs<T> g{};
-    g.M = N;
-    g.N = N;
+    g.M = Nt;
+    g.N = Ns;
     g.nseg = 1;
-    g.seg[0] = SegS<T>{Xc, D, 1, U, D, 1, (int)D};
-    EpiW<T, 128> e{(const T*)cs.B.get(), N, pd, Wn, N, w.wpart.as<double>(), ntn, N, N};
-    gemm_scalar_kernel<T, 128, 128, 16, true, true, EpiW<T, 128>><<<dim3(ntn, ntn), 256, 0, st>>>(g, e);
+    g.seg[0] = SegS<T>{Xt, D, 1, U, D, 1, (int)D};
+    EpiW<T, 128> e{Bc, Ns, a.pd, Wn, Ns, a.wpart, ntn, Nt, Ns};
+    gemm_scalar_kernel<T, 128, 128, 16, true, true, EpiW<T, 128>><<<dim3(ntn, cdiv(Nt, 128)), 256, 0, st>>>(g, e);
     LAUNCHCHK();
   }
   mark(ev, 3, st);
-  {
-    ScalarArgs<T> g{};
-    g.M = N;
-    g.N = (int)D;
-    g.nseg = 2;
-    g.seg[0] = SegS<T>{(const T*)cs.dA_hi.get(), N, 1, U, 1, D, N};
-    g.seg[1] = SegS<T>{Wn, N, 1, Xc, 1, D, N};
-    EpiG<128> e{sv, s->Xc.as<double>(), D, w.wpart.as<double>(), ntn, s->a0, w.G.as<double>(), D, N, (int)D};
-    gemm_scalar_kernel<T, 128, 128, 16, true, false, EpiG<128>><<<dim3(cdiv(D, 128), ntn), 256, 0, st>>>(g, e);
+  ScalarArgs<T> g{};
+  g.M = Nt;
+  g.N = (int)D;
+  g.nseg = 2;
+  g.seg[0] = SegS<T>{dA, Ns, 1, U, 1, D, Ns};
+  g.seg[1] = SegS<T>{Wn, Ns, 1, Xs, 1, D, Ns};
+  const int64_t tiles = (int64_t)cdiv(D, 128) * cdiv(Nt, 128);
+  int splits = pick_splits(tiles, 2 * (int64_t)cdiv(Ns, 16));
+  while (splits > 1 && (size_t)splits * Nt * D * sizeof(T) > a.part_bytes) splits >>= 1;
+  if (splits == 1) {
+    EpiG<128> e{a.s, a.Xt64, D, a.wpart, ntn, a.a0, a.G, D, Nt, (int)D};
+    gemm_scalar_kernel<T, 128, 128, 16, true, false, EpiG<128>><<<dim3(cdiv(D, 128), cdiv(Nt, 128)), 256, 0, st>>>(g, e);
+    LAUNCHCHK();
+  } else {
+    EpiPart<T> e{static_cast<T*>(a.part), D, Nt, (int)D};
+    gemm_scalar_kernel<T, 128, 128, 16, true, false, EpiPart<T>><<<dim3(cdiv(D, 128), cdiv(Nt, 128), splits), 256, 0, st>>>(g, e);
+    LAUNCHCHK();
+    k_g_reduce<T><<<Nt, 256, 0, st>>>(static_cast<const T*>(a.part), splits, Nt, D, a.s, a.Xt64, a.wpart, ntn, a.a0, a.G);
     LAUNCHCHK();
   }
 }
 
 template <bool X3>
-static void mvm_bf16(ffk_system* s, int prec, const double* pd, const double* sv, hipStream_t st, hipEvent_t* ev) {
+static void mvm_gemms_bf16(ffk_system* s, int prec, const MvmArgs& a, hipStream_t st, hipEvent_t* ev) {
   const int64_t N = s->N, D = s->D;
   const int64_t Nr = rup(N, 128), Dk = rup(D, 64), Dr = rup(D, 128);
   MvmWork& w = s->work;
@@ -322,37 +396,49 @@ static void mvm_bf16(ffk_system* s, int prec, const double* pd, const double* sv
     Bf16Args g{};
     g.nseg = 1;
     g.seg[0] = SegB{s->Xch.as<bf16_t>(), s->Xcl.as<bf16_t>(), w.Uh.as<bf16_t>(), w.Ul.as<bf16_t>(), Dk, Dk, (int)Dk};
-    EpiWbf<128, X3> e{cs.B.as<float>(), Nr, pd, w.Wnh.as<bf16_t>(), w.Wnl.as<bf16_t>(), w.wpart.as<double>(), ntn, (int)N};
+    EpiWbf<128, X3> e{cs.B.as<float>(), Nr, a.pd, w.Wnh.as<bf16_t>(), w.Wnl.as<bf16_t>(), a.wpart, ntn, (int)N};
     gemm_bf16_kernel<128, 128, 64, X3, EpiWbf<128, X3>><<<dim3(ntn, ntn), 256, 0, st>>>(g, e);
     LAUNCHCHK();
   }
   mark(ev, 3, st);
-  {
-    Bf16Args g{};
-    g.nseg = 2;
-    g.seg[0] = SegB{cs.dA_hi.as<bf16_t>(), cs.dA_lo.as<bf16_t>(), w.UTh.as<bf16_t>(), w.UTl.as<bf16_t>(), Nr, Nr, (int)Nr};
-    g.seg[1] = SegB{w.Wnh.as<bf16_t>(), w.Wnl.as<bf16_t>(), s->XcTh.as<bf16_t>(), s->XcTl.as<bf16_t>(), Nr, Nr, (int)Nr};
-    EpiG<128> e{sv, s->Xc.as<double>(), D, w.wpart.as<double>(), ntn, s->a0, w.G.as<double>(), D, (int)N, (int)D};
+  Bf16Args g{};
+  g.nseg = 2;
+  g.seg[0] = SegB{cs.dA_hi.as<bf16_t>(), cs.dA_lo.as<bf16_t>(), w.UTh.as<bf16_t>(), w.UTl.as<bf16_t>(), Nr, Nr, (int)Nr};
+  g.seg[1] = SegB{w.Wnh.as<bf16_t>(), w.Wnl.as<bf16_t>(), s->XcTh.as<bf16_t>(), s->XcTl.as<bf16_t>(), Nr, Nr, (int)Nr};
+  const int64_t tiles = (Dr / 128) * ntn;
+  int splits = pick_splits(tiles, 2 * Nr / 64);
+  while (splits > 1 && (size_t)splits * N * D * sizeof(float) > a.part_bytes) splits >>= 1;
+  if (splits == 1) {
+    EpiG<128> e{a.s, a.Xt64, D, a.wpart, ntn, a.a0, a.G, D, (int)N, (int)D};
     gemm_bf16_kernel<128, 128, 64, X3, EpiG<128>><<<dim3(Dr / 128, ntn), 256, 0, st>>>(g, e);
+    LAUNCHCHK();
+  } else {
+    EpiPart<float> e{static_cast<float*>(a.part), D, (int)N, (int)D};
+    gemm_bf16_kernel<128, 128, 64, X3, EpiPart<float>><<<dim3(Dr / 128, ntn, splits), 256, 0, st>>>(g, e);
+    LAUNCHCHK();
+    k_g_reduce<float><<<N, 256, 0, st>>>(static_cast<const float*>(a.part), splits, N, D, a.s, a.Xt64, a.wpart, ntn,
+                                         a.a0, a.G);
     LAUNCHCHK();
   }
 }
 
-void k_split_transpose_launch(const double* a, int64_t rows, int64_t cols, int64_t lda, int64_t cols_p,
-                              int64_t ld_out, bf16_t* hi, bf16_t* lo, hipStream_t st);
+static size_t part_budget(int64_t N, int64_t D) { return (size_t)16 * N * D * sizeof(double); }
 
 static void ensure_work(ffk_system* s, int prec, hipStream_t st) {
   const int64_t N = s->N, D = s->D;
   MvmWork& w = s->work;
-  if (!w.U64) {
-    w.U64.alloc(N * D * 8);
+  if (!w.pd) {
     w.pd.alloc(N * 8);
     w.s.alloc(D * 8);
-    w.spart.alloc((int64_t)cdiv(N, 256) * D * 8);
+    w.spart.alloc((int64_t)cdiv(N, GT) * D * 8);
     w.G.alloc(N * D * 8);
     w.wpart.alloc(N * (rup(N, 128) / 128) * 8);
+    w.part.alloc(part_budget(N, D));
   }
-  if (prec == FFK_FP64 && !w.Wn64) w.Wn64.alloc(N * N * 8);
+  if (prec == FFK_FP64 && !w.U64) {
+    w.U64.alloc(N * D * 8);
+    w.Wn64.alloc(N * N * 8);
+  }
   if (prec == FFK_FP32 && !w.U32) {
     w.U32.alloc(N * D * 4);
     w.Wn32.alloc(N * N * 4);
@@ -361,10 +447,13 @@ static void ensure_work(ffk_system* s, int prec, hipStream_t st) {
     const int64_t Nr = rup(N, 128), Dk = rup(D, 64), Dr = rup(D, 128);
     w.Uh.alloc(Nr * Dk * 2);
     w.Ul.alloc(Nr * Dk * 2);
-    HIPCHK(hipMemsetAsync(w.Uh.get(), 0, Nr * Dk * 2, st));
-    HIPCHK(hipMemsetAsync(w.Ul.get(), 0, Nr * Dk * 2, st));
     w.UTh.alloc(Dr * Nr * 2);
     w.UTl.alloc(Dr * Nr * 2);
+    // padding rows/columns stay zero: the front kernel writes only the valid part
+    HIPCHK(hipMemsetAsync(w.Uh.get(), 0, Nr * Dk * 2, st));
+    HIPCHK(hipMemsetAsync(w.Ul.get(), 0, Nr * Dk * 2, st));
+    HIPCHK(hipMemsetAsync(w.UTh.get(), 0, Dr * Nr * 2, st));
+    HIPCHK(hipMemsetAsync(w.UTl.get(), 0, Dr * Nr * 2, st));
     w.Wnh.alloc(Nr * Nr * 2);
     w.Wnl.alloc(Nr * Nr * 2);
   }
@@ -381,39 +470,44 @@ void kernel_mvm_ev(ffk_system* s, const double* v, double* y, double shift, int 
   const int M = s->M;
   MvmWork& w = s->work;
   const bool bf = (prec == FFK_BF16 || prec == FFK_BF16X3);
-  const int64_t ldu = rup(D, 64);
-  const size_t shm = 6 * M * sizeof(double);
-  if (prec == FFK_FP32)
-    k_jv<true, false><<<N, 256, shm, st>>>(s->R.as<double>(), s->pairs.as<int>(), v, s->Xc.as<double>(), M, D,
-                                           w.U64.as<double>(), w.pd.as<double>(), w.U32.as<float>(), nullptr,
-                                           nullptr, 0);
-  else if (bf)
-    k_jv<false, true><<<N, 256, shm, st>>>(s->R.as<double>(), s->pairs.as<int>(), v, s->Xc.as<double>(), M, D,
-                                           w.U64.as<double>(), w.pd.as<double>(), nullptr, w.Uh.as<bf16_t>(),
-                                           w.Ul.as<bf16_t>(), ldu);
+  const int64_t Nr = rup(N, 128), ldu = rup(D, 64);
+  const int nblk = cdiv(N, GT);
+  const size_t shm = (size_t)2 * GT * 3 * M * sizeof(double);
+  double* pd = w.pd.as<double>();
+  double* cp = w.spart.as<double>();
+  if (prec == FFK_FP64)
+    k_jv_tile<true, false, false><<<nblk, 256, shm, st>>>(s->R.as<double>(), s->pairs.as<int>(), v, s->Xc.as<double>(),
+                                                          N, M, D, w.U64.as<double>(), nullptr, nullptr, nullptr, 0,
+                                                          nullptr, nullptr, 0, pd, cp);
+  else if (prec == FFK_FP32)
+    k_jv_tile<false, true, false><<<nblk, 256, shm, st>>>(s->R.as<double>(), s->pairs.as<int>(), v, s->Xc.as<double>(),
+                                                          N, M, D, nullptr, w.U32.as<float>(), nullptr, nullptr, 0,
+                                                          nullptr, nullptr, 0, pd, cp);
   else
-    k_jv<false, false><<<N, 256, shm, st>>>(s->R.as<double>(), s->pairs.as<int>(), v, s->Xc.as<double>(), M, D,
-                                            w.U64.as<double>(), w.pd.as<double>(), nullptr, nullptr, nullptr, 0);
+    k_jv_tile<false, false, true><<<nblk, 256, shm, st>>>(s->R.as<double>(), s->pairs.as<int>(), v, s->Xc.as<double>(),
+                                                          N, M, D, nullptr, nullptr, w.Uh.as<bf16_t>(),
+                                                          w.Ul.as<bf16_t>(), ldu, w.UTh.as<bf16_t>(),
+                                                          w.UTl.as<bf16_t>(), Nr, pd, cp);
   LAUNCHCHK();
   mark(ev, 1, st);
-  colsum(w.U64.as<double>(), N, D, w.spart.as<double>(), w.s.as<double>(), 1.0, st);
-  const double* pd = w.pd.as<double>();
-  const double* sv = w.s.as<double>();
+  k_colsum_final<<<cdiv(D, 64), 256, 0, st>>>(cp, nblk, D, w.s.as<double>());
+  LAUNCHCHK();
+  mark(ev, 2, st);
+  MvmArgs a{N, N, D, s->a0, s->Xc.as<double>(), pd, w.s.as<double>(), w.wpart.as<double>(), w.G.as<double>(),
+            w.part.get(), w.part.bytes()};
+  CoeffSet& cs = s->coef[prec];
   if (prec == FFK_FP64) {
-    mark(ev, 2, st);
-    mvm_scalar<double>(s, prec, pd, sv, st, ev);
+    mvm_gemms_scalar<double>(a, s->Xc.as<double>(), s->Xc.as<double>(), w.U64.as<double>(), cs.dA_hi.as<double>(),
+                             cs.B.as<double>(), w.Wn64.as<double>(), st, ev);
   } else if (prec == FFK_FP32) {
-    mark(ev, 2, st);
-    mvm_scalar<float>(s, prec, pd, sv, st, ev);
+    mvm_gemms_scalar<float>(a, s->Xc32.as<float>(), s->Xc32.as<float>(), w.U32.as<float>(), cs.dA_hi.as<float>(),
+                            cs.B.as<float>(), w.Wn32.as<float>(), st, ev);
+  } else if (prec == FFK_BF16X3) {
+    mvm_gemms_bf16<true>(s, prec, a, st, ev);
   } else {
-    const int64_t Nr = rup(N, 128), Dr = rup(D, 128);
-    k_split_transpose_launch(w.U64.as<double>(), N, D, D, Dr, Nr, w.UTh.as<bf16_t>(), w.UTl.as<bf16_t>(), st);
-    mark(ev, 2, st);
-    if (prec == FFK_BF16X3)
-      mvm_bf16<true>(s, prec, pd, sv, st, ev);
-    else
-      mvm_bf16<false>(s, prec, pd, sv, st, ev);
+    mvm_gemms_bf16<false>(s, prec, a, st, ev);
   }
+  (void)bf;
   mark(ev, 4, st);
   const int tb = M <= 64 ? 64 : 128;
   k_jtg<<<N, tb, (3 * M + D) * sizeof(double), st>>>(s->R.as<double>(), w.G.as<double>(), v, shift, M, D, y);
@@ -425,8 +519,9 @@ void kernel_mvm(ffk_system* s, const double* v, double* y, double shift, int pre
   kernel_mvm_ev(s, v, y, shift, prec, st, nullptr);
 }
 
-// Average time of each phase over `iters` products: [J v, column sums (+ bf16
-// transposes), GEMM 1 + W epilogue, GEMM 2 + G epilogue, J^T G].
+// Average time of each phase over `iters` products: [J v (+ copies, column
+// partials), column-sum reduction, GEMM 1 + W epilogue, GEMM 2 + G epilogue
+// (+ split-K reduction), J^T G].
 void kernel_mvm_phases(ffk_system* s, const double* v, double* y, double shift, int prec, int iters, double* ms,
                        hipStream_t st) {
   hipEvent_t ev[6];
@@ -469,17 +564,18 @@ void kernel_predict(const ffk_system* tr, const ffk_system* te, const double* al
   require(tr->sigma == te->sigma, "kernel_predict: sigma differs");
   const int64_t Ns = tr->N, Nt = te->N, D = tr->D;
   const int M = tr->M;
-  DBuf U(Ns * D * 8), pd(Ns * 8), sv(D * 8), spart((int64_t)cdiv(Ns, 256) * D * 8);
+  const int nblk = cdiv(Ns, GT);
+  DBuf U(Ns * D * 8), pd(Ns * 8), sv(D * 8), cpart((int64_t)nblk * D * 8);
   DBuf Xt(Nt * D * 8), sqt(Nt * 8), dA(Nt * Ns * 8), B(Nt * Ns * 8), Wn(Nt * Ns * 8);
   const int ntn = cdiv(Ns, 128);
-  DBuf wpart(Nt * ntn * 8), G(Nt * D * 8);
-  k_jv<false, false><<<Ns, 256, 6 * M * sizeof(double), st>>>(tr->R.as<double>(), tr->pairs.as<int>(), alpha,
-                                                              tr->Xc.as<double>(), M, D, U.as<double>(),
-                                                              pd.as<double>(), nullptr, nullptr, nullptr, 0);
+  DBuf wpart(Nt * ntn * 8), G(Nt * D * 8), part(part_budget(Nt, D));
+  k_jv_tile<true, false, false><<<nblk, 256, (size_t)2 * GT * 3 * M * sizeof(double), st>>>(
+      tr->R.as<double>(), tr->pairs.as<int>(), alpha, tr->Xc.as<double>(), Ns, M, D, U.as<double>(), nullptr, nullptr,
+      nullptr, 0, nullptr, nullptr, 0, pd.as<double>(), cpart.as<double>());
   LAUNCHCHK();
-  colsum(U.as<double>(), Ns, D, spart.as<double>(), sv.as<double>(), 1.0, st);
-  k_center_with<<<Nt, 256, 0, st>>>(te->X.as<double>(), tr->xmean.as<double>(), D, Xt.as<double>(),
-                                    sqt.as<double>());
+  k_colsum_final<<<cdiv(D, 64), 256, 0, st>>>(cpart.as<double>(), nblk, D, sv.as<double>());
+  LAUNCHCHK();
+  k_center_with<<<Nt, 256, 0, st>>>(te->X.as<double>(), tr->xmean.as<double>(), D, Xt.as<double>(), sqt.as<double>());
   LAUNCHCHK();
   {
     ScalarArgs<double> g{};
@@ -492,28 +588,10 @@ void kernel_predict(const ffk_system* tr, const ffk_system* te, const double* al
     gemm_scalar_kernel<double, 128, 128, 16, true, true, EpiCoeffRect><<<dim3(ntn, cdiv(Nt, 128)), 256, 0, st>>>(g, e);
     LAUNCHCHK();
   }
-  {
-    ScalarArgs<double> g{};
-    g.M = (int)Nt;
-    g.N = (int)Ns;
-    g.nseg = 1;
-    g.seg[0] = SegS<double>{Xt.as<double>(), D, 1, U.as<double>(), D, 1, (int)D};
-    EpiW<double, 128> e{B.as<double>(), Ns, pd.as<double>(), Wn.as<double>(), Ns, wpart.as<double>(), ntn,
-                        (int)Nt, (int)Ns};
-    gemm_scalar_kernel<double, 128, 128, 16, true, true, EpiW<double, 128>><<<dim3(ntn, cdiv(Nt, 128)), 256, 0, st>>>(g, e);
-    LAUNCHCHK();
-  }
-  {
-    ScalarArgs<double> g{};
-    g.M = (int)Nt;
-    g.N = (int)D;
-    g.nseg = 2;
-    g.seg[0] = SegS<double>{dA.as<double>(), Ns, 1, U.as<double>(), 1, D, (int)Ns};
-    g.seg[1] = SegS<double>{Wn.as<double>(), Ns, 1, tr->Xc.as<double>(), 1, D, (int)Ns};
-    EpiG<128> e{sv.as<double>(), Xt.as<double>(), D, wpart.as<double>(), ntn, tr->a0, G.as<double>(), D, (int)Nt, (int)D};
-    gemm_scalar_kernel<double, 128, 128, 16, true, false, EpiG<128>><<<dim3(cdiv(D, 128), cdiv(Nt, 128)), 256, 0, st>>>(g, e);
-    LAUNCHCHK();
-  }
+  MvmArgs a{Nt, Ns, D, tr->a0, Xt.as<double>(), pd.as<double>(), sv.as<double>(), wpart.as<double>(), G.as<double>(),
+            part.get(), part.bytes()};
+  mvm_gemms_scalar<double>(a, Xt.as<double>(), tr->Xc.as<double>(), U.as<double>(), dA.as<double>(), B.as<double>(),
+                           Wn.as<double>(), st, nullptr);
   const int tb = M <= 64 ? 64 : 128;
   k_jtg<<<Nt, tb, (3 * M + D) * sizeof(double), st>>>(te->R.as<double>(), G.as<double>(), nullptr, 0.0, M, D, F);
   LAUNCHCHK();

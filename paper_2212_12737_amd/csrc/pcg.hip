@@ -12,6 +12,11 @@
 // improvement for 30 refreshes moves the product one rung up the ladder
 // BF16 -> BF16X3 -> FP32 -> FP64 and restarts from the best iterate.
 // `flexible` switches beta to Polak-Ribiere, -gamma z^T q / rho.
+// `switch_below` > 0 runs the first iterations with FP64 products and moves to
+// the reduced precision once the residual has fallen below switch_below |F|
+// (accurate products while the residual is large, cheap ones afterwards).
+// A breakdown (p^T q <= 0) under a reduced-precision product escalates like a
+// stagnating refresh when `escalate` is set.
 #include <chrono>
 
 #include "common.hpp"
@@ -132,6 +137,9 @@ ffk_status pcg_solve(ffk_system* s, const ffk_precond* P, const double* F, doubl
   HIPCHK(hipMemcpyAsync(R, F, n * 8, hipMemcpyDeviceToDevice, st));
   HIPCHK(hipMemcpyAsync(best.get(), alpha, n * 8, hipMemcpyDeviceToDevice, st));
   int prec = o->prec;
+  bool hi_phase = o->switch_below > 0.0 && prec != FFK_FP64;
+  int64_t switch_iter = hi_phase ? -1 : 0;
+  int64_t esc_iter[3] = {-1, -1, -1};
   int rho = S_RHO0;
   auto restart_direction = [&]() {
     apply_prec(R, Z);
@@ -151,10 +159,21 @@ ffk_status pcg_solve(ffk_system* s, const ffk_precond* P, const double* F, doubl
   }
   int64_t hist_len = 0;
   const int refresh = o->refresh_every;
+  auto escalate_now = [&]() {
+    if (n_esc < 3) esc_iter[n_esc] = it;
+    prec = next_rung(prec);
+    ++n_esc;
+    HIPCHK(hipMemcpyAsync(alpha, best.get(), n * 8, hipMemcpyDeviceToDevice, st));
+    true_residual();
+    ++n_ref;
+    since_best = 0;
+    restart_direction();
+  };
   while (status == FFK_NOT_CONVERGED && it < max_iter) {
+    const int cur = hi_phase ? FFK_FP64 : prec;
     {
       Timer tm(timing, st, &t_mvm);
-      kernel_mvm(s, Pv, Q, lam, prec, st);
+      kernel_mvm(s, Pv, Q, lam, cur, st);
     }
     {
       Timer tm(timing, st, &t_vec);
@@ -168,13 +187,21 @@ ffk_status pcg_solve(ffk_system* s, const ffk_precond* P, const double* F, doubl
     ++it;
     const double pap = hs[0], rr = hs[1];
     if (!(pap > 0.0) || !std::isfinite(pap) || !std::isfinite(rr)) {
+      if (o->escalate && cur != FFK_FP64) {
+        escalate_now();
+        continue;
+      }
       status = FFK_ERR_BREAKDOWN;
       break;
     }
     rel_upd = sqrt(rr) / fnorm;
+    if (hi_phase && rel_upd <= o->switch_below) {
+      hi_phase = false;
+      switch_iter = it;
+    }
     if (rep && rep->hist_host && hist_len < rep->hist_cap) rep->hist_host[hist_len++] = rel_upd;
     const bool candidate = rel_upd <= o->tol;
-    const bool periodic = refresh > 0 && (it % refresh) == 0 && prec != FFK_FP64;
+    const bool periodic = refresh > 0 && (it % refresh) == 0 && cur != FFK_FP64;
     if (candidate || periodic) {
       const double tr = true_residual();
       ++n_ref;
@@ -191,13 +218,8 @@ ffk_status pcg_solve(ffk_system* s, const ffk_precond* P, const double* F, doubl
       } else {
         ++since_best;
       }
-      if (o->escalate && prec != FFK_FP64 && (tr > 100.0 * best_true || since_best >= 30)) {
-        prec = next_rung(prec);
-        ++n_esc;
-        HIPCHK(hipMemcpyAsync(alpha, best.get(), n * 8, hipMemcpyDeviceToDevice, st));
-        true_residual();
-        since_best = 0;
-        restart_direction();
+      if (o->escalate && cur != FFK_FP64 && (tr > 100.0 * best_true || since_best >= 30)) {
+        escalate_now();
         continue;
       }
     }
@@ -226,8 +248,10 @@ ffk_status pcg_solve(ffk_system* s, const ffk_precond* P, const double* F, doubl
     rep->n_escalations = n_esc;
     rep->rel_res_true = rel_true;
     rep->rel_res_updated = rel_upd;
-    rep->final_prec = prec;
+    rep->final_prec = hi_phase ? FFK_FP64 : prec;
     rep->status = status;
+    rep->switch_iter = switch_iter;
+    for (int e = 0; e < 3; ++e) rep->esc_iter[e] = esc_iter[e];
     rep->t_mvm_ms = t_mvm;
     rep->t_prec_ms = t_prec;
     rep->t_vec_ms = t_vec;

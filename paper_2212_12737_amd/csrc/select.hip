@@ -329,8 +329,9 @@ void leverage_estimate(ffk_system* s, const int64_t* pilot, int64_t ns, double l
                        hipStream_t st) {
   const int64_t n = s->n;
   DBuf L0(n * ns * 8), diag(n * 8), flag(n);
+  HIPCHK(hipMemsetAsync(L0.get(), 0, n * ns * 8, st));
   std::vector<char> kept;
-  icd_forced(s, pilot, ns, lambda, L0.as<double>(), &kept, st);
+  icd_forced(s, pilot, ns, lambda, L0.as<double>(), n, &kept, st);
   kernel_diag(s, diag.as<double>(), st);
   HIPCHK(hipMemsetAsync(flag.get(), 0, n, st));
   k_mark<<<cdiv(ns, 256), 256, 0, st>>>(pilot, ns, flag.as<unsigned char>());

@@ -34,13 +34,14 @@ class FfkError(RuntimeError):
 class PcgOpts(ctypes.Structure):
     _fields_ = [("lam", ctypes.c_double), ("tol", ctypes.c_double), ("max_iter", ctypes.c_int64),
                 ("prec", ctypes.c_int32), ("refresh_every", ctypes.c_int32), ("escalate", ctypes.c_int32),
-                ("flexible", ctypes.c_int32), ("timing", ctypes.c_int32)]
+                ("flexible", ctypes.c_int32), ("timing", ctypes.c_int32), ("switch_below", ctypes.c_double)]
 
 
 class PcgReport(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int64), ("n_refresh", ctypes.c_int64), ("n_escalations", ctypes.c_int64),
                 ("rel_res_true", ctypes.c_double), ("rel_res_updated", ctypes.c_double),
                 ("final_prec", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("switch_iter", ctypes.c_int64), ("esc_iter", ctypes.c_int64 * 3),
                 ("t_mvm_ms", ctypes.c_double), ("t_prec_ms", ctypes.c_double), ("t_vec_ms", ctypes.c_double),
                 ("t_refresh_ms", ctypes.c_double), ("t_total_ms", ctypes.c_double),
                 ("hist_host", ctypes.POINTER(ctypes.c_double)), ("hist_cap", ctypes.c_int64),
@@ -289,15 +290,17 @@ class Report:
     t_refresh_ms: float
     t_total_ms: float
     hist: list
+    switch_iter: int = -1
+    esc_iter: tuple = ()
 
 
 def pcg_solve(ctx: Context, sys: System, P: Precond | None, F: torch.Tensor, lam: float, tol: float = 1e-6,
               max_iter: int = 0, prec: int = FP64, refresh_every: int = 10, escalate: bool = True,
               flexible: bool = False, timing: bool = False, hist_cap: int = 0, alpha: torch.Tensor | None = None,
-              stream=None):
+              switch_below: float = 0.0, stream=None):
     if alpha is None:
         alpha = torch.empty(sys.n, dtype=torch.float64, device=ctx.torch_device)
-    o = PcgOpts(lam, tol, max_iter, prec, refresh_every, int(escalate), int(flexible), int(timing))
+    o = PcgOpts(lam, tol, max_iter, prec, refresh_every, int(escalate), int(flexible), int(timing), switch_below)
     rep = PcgReport()
     hist = (ctypes.c_double * hist_cap)() if hist_cap > 0 else None
     if hist is not None:
@@ -308,7 +311,7 @@ def pcg_solve(ctx: Context, sys: System, P: Precond | None, F: torch.Tensor, lam
                                        _stream(stream)), "pcg_solve")
     r = Report(st, rep.iters, rep.n_refresh, rep.n_escalations, rep.rel_res_true, rep.rel_res_updated,
                rep.final_prec, rep.t_mvm_ms, rep.t_prec_ms, rep.t_vec_ms, rep.t_refresh_ms, rep.t_total_ms,
-               list(hist[:rep.hist_len]) if hist is not None else [])
+               list(hist[:rep.hist_len]) if hist is not None else [], rep.switch_iter, tuple(rep.esc_iter))
     return alpha, r
 
 
