@@ -242,6 +242,21 @@ ffk_status ffk_mlp_adam_step(ffk_ctx* ctx, ffk_mlp* net, const float* grad_dev, 
 ffk_status ffk_mlp_scores(ffk_ctx* ctx, const ffk_mlp* net, const ffk_system* sys,
                           double* scores_dev, void* stream);
 
+/* Training-data helpers for the score network.
+ * ffk_block_log_scores: per-geometry targets from column scores tau_dev
+ *   (n = 3 M N float64): y_g = log(sum_{c in geometry g} tau_c) minus the mean
+ *   over the N geometries, written to y_dev (N floats).
+ * ffk_mlp_prepare_inputs: the system's descriptor rows as floats (N x D
+ *   row-major) in X_dev, standardised with the network's mean / inverse std
+ *   when `standardize` is 1, raw otherwise.
+ * ffk_mlp_fit_norm: set the network's standardisation to the column mean and
+ *   inverse standard deviation of the B raw rows X_dev (B x D floats). */
+ffk_status ffk_block_log_scores(ffk_ctx* ctx, const double* tau_dev, int64_t N, int32_t M, float* y_dev,
+                                void* stream);
+ffk_status ffk_mlp_prepare_inputs(ffk_ctx* ctx, const ffk_mlp* net, const ffk_system* sys, float* X_dev,
+                                  int32_t standardize, void* stream);
+ffk_status ffk_mlp_fit_norm(ffk_ctx* ctx, ffk_mlp* net, const float* X_dev, int64_t B, void* stream);
+
 /* ---- rule of thumb (section 4.3, Eq. 8) ---------------------------------- */
 
 /* k_RoT = (k_min^m m n^2 / 2)^(1/(2+m)), rounded to the nearest integer in [1, n]. */

@@ -353,6 +353,34 @@ ffk_status ffk_mlp_scores(ffk_ctx* ctx, const ffk_mlp* net, const ffk_system* s,
   });
 }
 
+ffk_status ffk_block_log_scores(ffk_ctx* ctx, const double* tau, int64_t N, int32_t M, float* y, void* stream) {
+  if (!ctx || !tau || !y) return FFK_ERR_ARG;
+  return guarded(ctx, [&]() {
+    require(N >= 1 && M >= 3, "block_log_scores: need N >= 1 and M >= 3");
+    block_log_scores(tau, N, M, y, S(stream));
+    return FFK_OK;
+  });
+}
+
+ffk_status ffk_mlp_prepare_inputs(ffk_ctx* ctx, const ffk_mlp* net, const ffk_system* s, float* X, int32_t standardize,
+                                  void* stream) {
+  if (!ctx || !net || !s || !X) return FFK_ERR_ARG;
+  return guarded(ctx, [&]() {
+    require(net->D == s->D, "mlp_prepare_inputs: network input size differs from the descriptor size");
+    mlp_prepare_inputs(net, s, X, standardize, S(stream));
+    return FFK_OK;
+  });
+}
+
+ffk_status ffk_mlp_fit_norm(ffk_ctx* ctx, ffk_mlp* net, const float* X, int64_t B, void* stream) {
+  if (!ctx || !net || !X) return FFK_ERR_ARG;
+  return guarded(ctx, [&]() {
+    require(B >= 2, "mlp_fit_norm: need at least two rows");
+    mlp_fit_norm(net, X, B, S(stream));
+    return FFK_OK;
+  });
+}
+
 int64_t ffk_rule_of_thumb(int64_t n, double k_min, double m) {
   if (n < 1 || !(k_min > 0) || !(m > 0)) return -1;
   const double k = std::pow(std::pow(k_min, m) * m * (double)n * (double)n / 2.0, 1.0 / (2.0 + m));

@@ -282,6 +282,9 @@ void mlp_grad(ffk_mlp* net, const float* X, const float* y, int64_t B, float* lo
               hipStream_t st);
 void mlp_adam(ffk_mlp* net, const float* grad, float lr, hipStream_t st);
 void mlp_scores(const ffk_mlp* net, const ffk_system* sys, double* scores, hipStream_t st);
+void mlp_prepare_inputs(const ffk_mlp* net, const ffk_system* s, float* out, int standardize, hipStream_t st);
+void mlp_fit_norm(ffk_mlp* net, const float* X, int64_t B, hipStream_t st);
+void block_log_scores(const double* tau, int64_t N, int M, float* y, hipStream_t st);
 
 // rng shared by host and device code of the library
 __host__ __device__ inline uint64_t splitmix64_at(uint64_t seed, uint64_t counter) {

@@ -84,6 +84,9 @@ _SIGS = {
     "ffk_mlp_grad": (I32, [P, P, P, P, I64, P, P, P]),
     "ffk_mlp_adam_step": (I32, [P, P, P, FLT, P]),
     "ffk_mlp_scores": (I32, [P, P, P, P, P]),
+    "ffk_block_log_scores": (I32, [P, P, I64, I32, P, P]),
+    "ffk_mlp_prepare_inputs": (I32, [P, P, P, P, I32, P]),
+    "ffk_mlp_fit_norm": (I32, [P, P, P, I64, P]),
     "ffk_rule_of_thumb": (I64, [I64, DBL, DBL]),
 }
 
@@ -382,6 +385,26 @@ def mlp_scores(ctx: Context, net: Mlp, sys: System, stream=None) -> torch.Tensor
     s = torch.empty(sys.N, dtype=torch.float64, device=ctx.torch_device)
     ctx.check(lib().ffk_mlp_scores(ctx.h, net.h, sys.h, _ptr(s), _stream(stream)), "mlp_scores")
     return s
+
+
+def block_log_scores(ctx: Context, tau: torch.Tensor, N: int, M: int, stream=None) -> torch.Tensor:
+    y = torch.empty(N, dtype=torch.float32, device=ctx.torch_device)
+    ctx.check(lib().ffk_block_log_scores(ctx.h, _ptr(tau, torch.float64), N, M, _ptr(y), _stream(stream)),
+              "block_log_scores")
+    return y
+
+
+def mlp_prepare_inputs(ctx: Context, net: Mlp, sys: System, standardize: bool = True, out=None,
+                       stream=None) -> torch.Tensor:
+    X = out if out is not None else torch.empty((sys.N, sys.D), dtype=torch.float32, device=ctx.torch_device)
+    ctx.check(lib().ffk_mlp_prepare_inputs(ctx.h, net.h, sys.h, _ptr(X, torch.float32), int(standardize),
+                                           _stream(stream)), "mlp_prepare_inputs")
+    return X
+
+
+def mlp_fit_norm(ctx: Context, net: Mlp, X: torch.Tensor, stream=None):
+    ctx.check(lib().ffk_mlp_fit_norm(ctx.h, net.h, _ptr(X, torch.float32), X.shape[0], _stream(stream)),
+              "mlp_fit_norm")
 
 
 def rule_of_thumb(n: int, k_min: float = 100.0, m: float = 1.0) -> int:
