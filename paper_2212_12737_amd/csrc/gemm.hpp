@@ -58,6 +58,7 @@ struct FragCoord {
   int wm0, wn0, lane;   // absolute origin of this wave's sub-tile
   int m0, n0;           // absolute origin of the block tile
   bool f64;             // FP64 MFMA output layout
+  int tn;               // tile column index (n0 / BN)
   __device__ inline int row(int tm, int v) const {
     return wm0 + tm * 16 + (f64 ? 4 * v + (lane >> 4) : 4 * (lane >> 4) + v);
   }
@@ -179,7 +180,7 @@ __global__ __launch_bounds__(256) void gemm_scalar_kernel(ScalarArgs<TI> g, Epi 
     if (t + 1 < te) store(buf ^ 1);
     __syncthreads();
   }
-  FragCoord fc{m0 + wm0, n0 + wn0, lane, m0, n0, sizeof(T) == 8};
+  FragCoord fc{m0 + wm0, n0 + wn0, lane, m0, n0, sizeof(T) == 8, (int)blockIdx.x};
   epi.template run<T, TM, TN>(acc, fc, reinterpret_cast<char*>(&As[0][0][0]));
 }
 
@@ -302,8 +303,140 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(Bf16Args g, Epi epi) {
       __syncthreads();
     }
   }
-  FragCoord fc{m0 + wm0, n0 + wn0, lane, m0, n0, false};
+  FragCoord fc{m0 + wm0, n0 + wn0, lane, m0, n0, false, (int)blockIdx.x};
   epi.template run<float, TM, TN>(acc, fc, reinterpret_cast<char*>(&As[0][0]));
+}
+
+// ---------------------------------------------------------------------------
+// BF16 MFMA engine, pipelined through direct global->LDS loads (gfx950
+// global_load_lds_dwordx4).  Each wave-wide load moves 64 x 16 bytes into 1 KB
+// of LDS at base + lane*16, so a 16-row x 32-k operand block is fetched with
+// lane L taking row L%16 and 16-byte chunk L/16: exactly the lane layout the
+// 16x16x32 MFMA reads, hence every ds_read_b128 of an operand fragment is a
+// contiguous, conflict-free 1 KB read and no staging registers are needed.
+// S stages of BK = 32 keep S-1 tiles in flight behind the MFMAs.
+// ---------------------------------------------------------------------------
+// gfx9 s_waitcnt immediate for vmcnt(N): low bits [3:0], high bits [15:14];
+// expcnt and lgkmcnt left at "no wait".
+template <int N> struct VmCnt {
+  static constexpr unsigned v = (unsigned)((N & 0xF) | ((N >> 4) << 14) | (0x7 << 4) | (0xF << 8));
+};
+
+__device__ inline void dma16(const bf16_t* g, bf16_t* lds_base) {
+  __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1)))*)g,
+                                   (void __attribute__((address_space(3)))*)lds_base, 16, 0, 0);
+}
+
+// XCD-aware tile order: consecutive dispatch slots go to different XCDs
+// (round robin over 8); remap so each XCD works on a contiguous range of tiles,
+// grouped by 8 tile rows, so tiles that share operand rows share an L2.
+__device__ inline void tile_coords(int& tm, int& tn) {
+  const int nt_n = gridDim.x, nt_m = gridDim.y;
+  const int T = nt_m * nt_n;
+  int lin = blockIdx.y * nt_n + blockIdx.x;
+  if (T % 8 == 0) lin = (lin % 8) * (T / 8) + lin / 8;
+  const int G = 8;
+  const int per_group = G * nt_n;
+  const int grp = lin / per_group;
+  const int first = grp * G;
+  const int gsz = min(nt_m - first, G);
+  const int in = lin % per_group;
+  tm = first + in % gsz;
+  tn = in / gsz;
+}
+
+template <int BM, int BN, int S, bool X3, class Epi>
+__global__ __launch_bounds__(256) void gemm_bf16_dma_kernel(Bf16Args g, Epi epi) {
+  constexpr int BK = 32;
+  constexpr int NARR = X3 ? 2 : 1;
+  constexpr int GROUP_BYTES = 1024;                     // 16 rows x 32 k x 2 B
+  constexpr int GA = BM / 16, GB = BN / 16;             // row groups per operand tile
+  constexpr int A_BYTES = GA * GROUP_BYTES;
+  constexpr int B_BYTES = GB * GROUP_BYTES;
+  constexpr int STAGE_BYTES = NARR * (A_BYTES + B_BYTES);
+  constexpr int QA = GA / 4, QB = GB / 4;               // groups loaded per wave
+  constexpr int LPT = NARR * (QA + QB);                 // wave-wide loads per tile per wave
+  constexpr int TM = BM / 32, TN = BN / 32;             // 16x16 blocks per wave (2 x 2 waves)
+  __shared__ __attribute__((aligned(1024))) char smem[S * STAGE_BYTES];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  int tmi, tni;
+  tile_coords(tmi, tni);
+  const int m0 = tmi * BM, n0 = tni * BN;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int t0 = g.seg[0].K / BK;
+  const int T_ = t0 + (g.nseg > 1 ? g.seg[1].K / BK : 0);
+  const int tb = (int)((int64_t)T_ * blockIdx.z / gridDim.z);
+  const int te = (int)((int64_t)T_ * (blockIdx.z + 1) / gridDim.z);
+
+  f4 acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[i][j] = f4{0, 0, 0, 0};
+
+  // lane L of a group load: row L%16, 16-byte chunk L/16
+  const int lrow = lane & 15, lchunk = lane >> 4;
+  auto issue = [&](int t) {
+    const SegB& sg = (t < t0) ? g.seg[0] : g.seg[1];
+    const int k0 = (t < t0 ? t : t - t0) * BK + lchunk * 8;
+    char* st = smem + (t % S) * STAGE_BYTES;
+#pragma unroll
+    for (int h = 0; h < NARR; ++h) {
+      const bf16_t* A = h ? sg.Al : sg.Ah;
+      const bf16_t* B = h ? sg.Bl : sg.Bh;
+#pragma unroll
+      for (int q = 0; q < QA; ++q) {
+        const int grp = wave * QA + q;
+        dma16(A + (int64_t)(m0 + grp * 16 + lrow) * sg.lda + k0,
+              reinterpret_cast<bf16_t*>(st + h * A_BYTES + grp * GROUP_BYTES));
+      }
+#pragma unroll
+      for (int q = 0; q < QB; ++q) {
+        const int grp = wave * QB + q;
+        dma16(B + (int64_t)(n0 + grp * 16 + lrow) * sg.ldb + k0,
+              reinterpret_cast<bf16_t*>(st + NARR * A_BYTES + h * B_BYTES + grp * GROUP_BYTES));
+      }
+    }
+  };
+
+#pragma unroll
+  for (int s = 0; s < S - 1; ++s)
+    if (tb + s < te) issue(tb + s);
+  for (int t = tb; t < te; ++t) {
+    // this wave's loads of tile t have landed; the barrier (without the
+    // memory fence of __syncthreads, which would drain every load in flight)
+    // makes that true for all waves and frees the stage written next
+    if (S > 2 && t + S - 2 < te) __builtin_amdgcn_s_waitcnt(VmCnt<LPT * (S > 2 ? S - 2 : 0)>::v);
+    else __builtin_amdgcn_s_waitcnt(VmCnt<0>::v);
+    asm volatile("s_barrier" ::: "memory");
+    if (t + S - 1 < te) issue(t + S - 1);
+    const char* st = smem + (t % S) * STAGE_BYTES;
+    u4 ah[TM], bh[TN], al[X3 ? TM : 1], bl[X3 ? TN : 1];
+#pragma unroll
+    for (int i = 0; i < TM; ++i) {
+      ah[i] = *reinterpret_cast<const u4*>(st + (wm * TM + i) * GROUP_BYTES + lane * 16);
+      if (X3) al[X3 ? i : 0] = *reinterpret_cast<const u4*>(st + A_BYTES + (wm * TM + i) * GROUP_BYTES + lane * 16);
+    }
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+      bh[j] = *reinterpret_cast<const u4*>(st + NARR * A_BYTES + (wn * TN + j) * GROUP_BYTES + lane * 16);
+      if (X3) bl[X3 ? j : 0] = *reinterpret_cast<const u4*>(st + NARR * A_BYTES + B_BYTES + (wn * TN + j) * GROUP_BYTES + lane * 16);
+    }
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        if (X3) {
+          acc[i][j] = mfma_bf16(al[X3 ? i : 0], bh[j], acc[i][j]);
+          acc[i][j] = mfma_bf16(ah[i], bl[X3 ? j : 0], acc[i][j]);
+        }
+        acc[i][j] = mfma_bf16(ah[i], bh[j], acc[i][j]);
+      }
+  }
+  __syncthreads();
+  FragCoord fc{m0 + wm * (BM / 2), n0 + wn * (BN / 2), lane, m0, n0, false, tni};
+  epi.template run<float, TM, TN>(acc, fc, smem);
 }
 
 // Shared LDS for epilogues that need it: the engines pass their operand LDS

@@ -198,7 +198,7 @@ struct EpiW {
     __syncthreads();
     for (int t = threadIdx.x; t < BM; t += blockDim.x) {
       const int r = f.m0 + t;
-      if (r < Nr) wpart[(int64_t)r * ntn + blockIdx.x] = red[t] + red[BM + t];
+      if (r < Nr) wpart[(int64_t)r * ntn + f.tn] = red[t] + red[BM + t];
     }
   }
 };
@@ -241,7 +241,7 @@ struct EpiWbf {
     __syncthreads();
     for (int t = threadIdx.x; t < BM; t += blockDim.x) {
       const int r = f.m0 + t;
-      if (r < N) wpart[(int64_t)r * ntn + blockIdx.x] = red[t] + red[BM + t];
+      if (r < N) wpart[(int64_t)r * ntn + f.tn] = red[t] + red[BM + t];
     }
   }
 };
@@ -397,7 +397,7 @@ static void mvm_gemms_bf16(ffk_system* s, int prec, const MvmArgs& a, hipStream_
     g.nseg = 1;
     g.seg[0] = SegB{s->Xch.as<bf16_t>(), s->Xcl.as<bf16_t>(), w.Uh.as<bf16_t>(), w.Ul.as<bf16_t>(), Dk, Dk, (int)Dk};
     EpiWbf<128, X3> e{cs.B.as<float>(), Nr, a.pd, w.Wnh.as<bf16_t>(), w.Wnl.as<bf16_t>(), a.wpart, ntn, (int)N};
-    gemm_bf16_kernel<128, 128, 64, X3, EpiWbf<128, X3>><<<dim3(ntn, ntn), 256, 0, st>>>(g, e);
+    gemm_bf16_dma_kernel<128, 128, 4, X3, EpiWbf<128, X3>><<<dim3(ntn, ntn), 256, 0, st>>>(g, e);
     LAUNCHCHK();
   }
   mark(ev, 3, st);
@@ -406,15 +406,15 @@ static void mvm_gemms_bf16(ffk_system* s, int prec, const MvmArgs& a, hipStream_
   g.seg[0] = SegB{cs.dA_hi.as<bf16_t>(), cs.dA_lo.as<bf16_t>(), w.UTh.as<bf16_t>(), w.UTl.as<bf16_t>(), Nr, Nr, (int)Nr};
   g.seg[1] = SegB{w.Wnh.as<bf16_t>(), w.Wnl.as<bf16_t>(), s->XcTh.as<bf16_t>(), s->XcTl.as<bf16_t>(), Nr, Nr, (int)Nr};
   const int64_t tiles = (Dr / 128) * ntn;
-  int splits = pick_splits(tiles, 2 * Nr / 64);
+  int splits = pick_splits(tiles, 2 * Nr / 32);
   while (splits > 1 && (size_t)splits * N * D * sizeof(float) > a.part_bytes) splits >>= 1;
   if (splits == 1) {
     EpiG<128> e{a.s, a.Xt64, D, a.wpart, ntn, a.a0, a.G, D, (int)N, (int)D};
-    gemm_bf16_kernel<128, 128, 64, X3, EpiG<128>><<<dim3(Dr / 128, ntn), 256, 0, st>>>(g, e);
+    gemm_bf16_dma_kernel<128, 128, 4, X3, EpiG<128>><<<dim3(Dr / 128, ntn), 256, 0, st>>>(g, e);
     LAUNCHCHK();
   } else {
     EpiPart<float> e{static_cast<float*>(a.part), D, (int)N, (int)D};
-    gemm_bf16_kernel<128, 128, 64, X3, EpiPart<float>><<<dim3(Dr / 128, ntn, splits), 256, 0, st>>>(g, e);
+    gemm_bf16_dma_kernel<128, 128, 4, X3, EpiPart<float>><<<dim3(Dr / 128, ntn, splits), 256, 0, st>>>(g, e);
     LAUNCHCHK();
     k_g_reduce<float><<<N, 256, 0, st>>>(static_cast<const float*>(a.part), splits, N, D, a.s, a.Xt64, a.wpart, ntn,
                                          a.a0, a.G);
