@@ -1,24 +1,30 @@
 #!/usr/bin/env python3
 """Benchmark of the hot path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config C2]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config C2] [--mvm-configs C5]
 
-Workload: the M=21, N=2000 system (n = 126000, D = 210, lambda = 1e-9,
-pivoted-Cholesky Nystroem k = 2000), seeded synthetic geometries and forces.
+Workload (default): M = 21 atoms, N = 2000 geometries (n = 126000 unknowns,
+D = 210 inverse distances), Matern-5/2 sigma = 10, lambda = 1e-9, Nystroem
+rank k = 2000 from pivoted-Cholesky selection; seeded synthetic geometries and
+Morse + Coulomb-like forces.
 
-A timed step is one matrix-free kernel product y = K v in the precision the
-mixed solver iterates with (BF16X3: split BF16 on MFMA, FP32 accumulation);
-the JSON `value` is its algorithmic throughput (6 N^2 D + 24 N D flops per
-product) over the K timed steps.  The same run measures, untimed by the step
-loop but with its own clock, the time to a 1e-6 true FP64 residual of the full
-solve (selection + preconditioner build + PCG) for the mixed path and for the
-plain FP64 path, the per-precision product rates, the per-phase breakdown
-that names the dominant kernel for the roofline entry, and the FP64 CPU
-oracle on a bounded sample of the same product.
+A timed step is one pass of the whole hot path on inputs already in HBM
+(positions R and forces F): descriptor and Hessian-coefficient build,
+column selection, preconditioner build (L stored FP32, FP64 k x k core) and
+the mixed-precision PCG solve (FP64 products until the residual is below
+1e-2 |F|, then split-BF16 MFMA products with an FP64 true-residual refresh
+every 10 iterations) to a true FP64 relative residual of 1e-6.  `value` is
+the mean wall time of one such solve (lower is better).  Beside it the run
+reports the plain FP64 solve of the same system (FP64 products, FP64 L), the
+kernel-product rates per precision (here and at the M = 60, N = 20000
+system), the per-kernel HIP-event clocks of the timed steps with the roofline
+entry of the kernel that took the most time, and the FP64 CPU oracle timed on
+a bounded sample of the same solve.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -29,6 +35,10 @@ sys.path.insert(0, ROOT)
 
 PEAK_TFLOPS = {"bf16": 2500.0, "bf16x3": 2500.0, "fp32": 157.3, "fp64": 78.6}
 PEAK_HBM_GBS = 8000.0
+TOL = 1e-6
+SWITCH_BELOW = 1e-2
+REFRESH = 10
+CLOCK_STRIDE = 16       # event pairs around every 16th launch of each clocked kernel
 
 
 def log(*a):
@@ -36,20 +46,23 @@ def log(*a):
 
 
 def mvm_flops(N: int, D: int) -> float:
+    """Algorithmic flops of one kernel product: 2N^2D (GEMM 1) + 4N^2D (GEMM 2) + 24ND (J v, J^T G)."""
     return 6.0 * N * N * D + 24.0 * N * D
 
 
-def phase_model(N: int, M: int, D: int, prec: str):
-    """Algorithmic work per launch of each product phase: (bound, amount, unit)."""
-    n = 3 * M * N
-    low = 4 if prec in ("bf16", "bf16x3") else (4 if prec == "fp32" else 0)
+def kernel_model(name: str, N: int, D: int, n: int, k: int, L_bytes: int):
+    """(bound, algorithmic amount per launch, unit) of each clocked kernel.
+
+    GEMMs count their algorithmic flops once, whatever the operand split;
+    the GEMVs count one pass over the stored L plus their input vector."""
     return {
-        "jv": ("hbm", 8.0 * (2 * n + 2 * N * D) + low * N * D, "B"),
-        "colsum": ("hbm", 8.0 * N * D + 4.0 * N * D * (prec in ("bf16", "bf16x3")), "B"),
         "gemm1": ("mfma", 2.0 * N * N * D, "flop"),
         "gemm2": ("mfma", 4.0 * N * N * D, "flop"),
+        "gemv_t": ("hbm", float(L_bytes) * n * k + 8.0 * n, "B"),
+        "gemv_n": ("hbm", float(L_bytes) * n * k + 8.0 * k, "B"),
+        "jv": ("hbm", 8.0 * (2 * n + N * D), "B"),
         "jtg": ("hbm", 8.0 * (N * D + 2 * n), "B"),
-    }
+    }.get(name)
 
 
 def time_mvm(ffk, ctx, S, v, prec, steps, warmup):
@@ -66,66 +79,142 @@ def time_mvm(ffk, ctx, S, v, prec, steps, warmup):
     return a.elapsed_time(b) / steps
 
 
-def solve(ffk, ctx, S, F, cfg, mixed: bool):
+def mvm_rates(ffk, ctx, cfg, S, v, steps, warmup):
+    fl = mvm_flops(cfg.N, cfg.D)
+    out = {}
+    for prec in ("bf16", "bf16x3", "fp32", "fp64"):
+        ms = time_mvm(ffk, ctx, S, v, ffk.PRECISIONS[prec], steps, warmup)
+        tf = fl / ms / 1e9
+        out[prec] = {"ms": ms, "tflops": tf, "frac_peak": tf / PEAK_TFLOPS[prec]}
+        log("mvm %s %-6s %9.4f ms %8.2f TFLOP/s (%.1f%% of the %s peak)"
+            % (cfg.name, prec, ms, tf, 100 * tf / PEAK_TFLOPS[prec], prec))
+    return out
+
+
+def solve(ffk, ctx, R, F, cfg, arm: str):
+    """One pass of the hot path from R and F in HBM; returns (alpha, record)."""
     import torch
+    mixed = arm != "fp64"
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    idx = ffk.nystrom_select(ctx, S, "pivchol", cfg.k, lam=cfg.lam, seed=cfg.sel_seed)
+    S = ffk.descriptor_build(ctx, R, cfg.sigma)
+    idx = ffk.nystrom_select(ctx, S, cfg.strategy, cfg.k, lam=cfg.lam, seed=cfg.sel_seed)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     P = ffk.precond_build(ctx, S, idx, cfg.lam, store=ffk.FP32 if mixed else ffk.FP64)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
-    alpha, rep = ffk.pcg_solve(ctx, S, P, F, cfg.lam, tol=1e-6, max_iter=50000,
-                               prec=ffk.BF16X3 if mixed else ffk.FP64, refresh_every=10, escalate=True)
+    prec = {"fp64": ffk.FP64, "mixed": ffk.BF16X3, "mixed_fp32": ffk.FP32}[arm]
+    alpha, rep = ffk.pcg_solve(ctx, S, P, F, cfg.lam, tol=TOL, max_iter=50000, prec=prec, refresh_every=REFRESH,
+                               escalate=True, switch_below=SWITCH_BELOW if mixed else 0.0)
     torch.cuda.synchronize()
     t3 = time.perf_counter()
-    return alpha, {
-        "precision": "bf16x3+fp64-refresh" if mixed else "fp64",
+    rec = {
+        "arm": arm,
+        "products": {"fp64": "fp64", "mixed": "fp64 until |r| < 1e-2 |F|, then bf16x3; fp64 refresh every 10",
+                     "mixed_fp32": "fp64 until |r| < 1e-2 |F|, then fp32; fp64 refresh every 10"}[arm],
         "L_storage": "fp32" if mixed else "fp64",
-        "k_eff": int(P.k_eff), "iters": int(rep.iters), "status": int(rep.status),
-        "rel_res_true": rep.rel_res_true, "n_refresh": int(rep.n_refresh),
+        "k_eff": int(P.k_eff), "iters": int(rep.iters), "switch_iter": int(rep.switch_iter),
+        "status": int(rep.status), "rel_res_true": rep.rel_res_true, "n_refresh": int(rep.n_refresh),
         "n_escalations": int(rep.n_escalations), "final_prec": int(rep.final_prec),
-        "t_select_s": t1 - t0, "t_build_s": t2 - t1, "t_pcg_s": t3 - t2, "t_total_s": t3 - t0,
+        "t_descriptor_select_s": t1 - t0, "t_build_s": t2 - t1, "t_pcg_s": t3 - t2, "t_total_s": t3 - t0,
     }
+    return alpha, rec
 
 
-def cpu_baseline(cfg, s, budget_s: float = 15.0):
+def source_digest(paths):
+    h = hashlib.sha256()
+    for p in paths:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+# sources whose kernels the HBM traffic figures below were taken from
+KERNEL_SOURCES = {
+    "gemv_t": ["paper_2212_12737_amd/csrc/precond.hip"],
+    "gemv_n": ["paper_2212_12737_amd/csrc/precond.hip"],
+    "gemm1": ["paper_2212_12737_amd/csrc/mvm.hip", "paper_2212_12737_amd/csrc/gemm.hpp"],
+    "gemm2": ["paper_2212_12737_amd/csrc/mvm.hip", "paper_2212_12737_amd/csrc/gemm.hpp"],
+}
+
+
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch from the committed counter summary, if its source digest still matches."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path) or kernel not in KERNEL_SOURCES:
+        return None
+    with open(path) as f:
+        tab = json.load(f)
+    e = tab.get(workload, {}).get(kernel)
+    if not e or e.get("source_digest") != source_digest(KERNEL_SOURCES[kernel]):
+        return None
+    return e["bytes_per_launch"]
+
+
+def cpu_baseline(cfg, s, iters: int, k: int, budget_s: float = 20.0):
+    """The FP64 oracle on a bounded sample of the same solve, on one core.
+
+    Sample: the oracle's matrix-free product over T target geometries (scaled
+    by N / T) plus its Woodbury apply with an L of n/8 rows (scaled by 8),
+    i.e. the oracle's time per PCG iteration, times the iteration count of
+    the plain FP64 GPU solve (equal in exact arithmetic).  Selection and
+    preconditioner build are left out, so this is a lower bound."""
     import numpy as np
+    from threadpoolctl import threadpool_limits
     import synth
     from oracle import kernel as ok
-    v = synth.random_vectors(s.R.size, 11)
-    N, D = cfg.N, cfg.D
-    t0 = time.perf_counter()
-    ok.kernel_mvm(s.R, s.R, v, cfg.sigma, targets=np.arange(8))
-    per_target = (time.perf_counter() - t0) / 8
-    T = int(max(8, min(N, budget_s / max(per_target, 1e-6))))
-    t0 = time.perf_counter()
-    ok.kernel_mvm(s.R, s.R, v, cfg.sigma, targets=np.arange(T))
-    dt = time.perf_counter() - t0
-    flops = mvm_flops(N, D) * T / N
-    return {"value": flops / dt / 1e12, "unit": "TFLOP/s", "cores": 1, "kind": "oracle",
-            "sample": "FP64 matrix-free oracle product, %d of %d target geometries (%.1f s), scaled per flop" % (T, N, dt),
-            "seconds_per_full_product": dt * N / T}
+    from oracle import solve as osv
+    with threadpool_limits(1):
+        v = synth.random_vectors(s.R.size, 11)
+        ok.kernel_mvm(s.R, s.R, v, cfg.sigma, targets=np.arange(2))
+        t0 = time.perf_counter()
+        ok.kernel_mvm(s.R, s.R, v, cfg.sigma, targets=np.arange(16))
+        per_target = (time.perf_counter() - t0) / 16
+        T = int(max(4, min(cfg.N, 0.6 * budget_s / max(per_target, 1e-6))))
+        t0 = time.perf_counter()
+        ok.kernel_mvm(s.R, s.R, v, cfg.sigma, targets=np.arange(T))
+        t_mvm = (time.perf_counter() - t0) * cfg.N / T
+        n = s.R.size
+        ns = max(k, n // 8)
+        rng = np.random.default_rng(0)
+        L = rng.standard_normal((ns, k)) * 1e-2
+        apply = osv.woodbury(L, cfg.lam)
+        r = rng.standard_normal(ns)
+        reps = 3
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            apply(r)
+        t_apply = (time.perf_counter() - t0) / reps * n / ns
+    per_iter = t_mvm + t_apply
+    return {"value": per_iter * iters, "unit": "s", "cores": 1, "kind": "oracle",
+            "sample": ("FP64 oracle on one core: matrix-free product over %d of %d target geometries (x%.0f) plus "
+                       "Woodbury apply with L of %d of %d rows (x%.1f) = %.3f s per PCG iteration, times the %d "
+                       "iterations of the FP64 GPU solve; selection and build excluded (lower bound)"
+                       % (T, cfg.N, cfg.N / T, ns, n, n / ns, per_iter, iters)),
+            "seconds_per_iteration": per_iter, "seconds_mvm": t_mvm, "seconds_apply": t_apply}
 
 
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=3, help="timed solves")
+    ap.add_argument("--warmup", type=int, default=1, help="untimed solves before the timed ones")
     ap.add_argument("--config", default="C2")
-    ap.add_argument("--no-pcg", action="store_true")
-    ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--extra-configs", default="", help="comma list of configs for extra MVM rates (e.g. C3,C5)")
+    ap.add_argument("--mvm-configs", default="C5", help="comma list of further systems for kernel-product rates")
+    ap.add_argument("--mvm-steps", type=int, default=20)
+    ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison solve")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle sample")
+    ap.add_argument("--kernels-only", type=int, default=0,
+                    help="counter-collection mode: build once, run this many preconditioner applies and products, "
+                         "plus a plain copy of known size for calibration; prints no JSON line")
     a = ap.parse_args(argv)
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if a.gpus != 1 or world != 1:
-        print("bench.py: this build runs on one GPU only (--gpus %d requested); the multi-GPU path is a design "
-              "note, not an implementation." % max(a.gpus, world), file=sys.stderr)
+        print("bench.py: runs on one GPU only (--gpus %d requested); how the solve would shard over several GPUs "
+              "is a design note, not part of this library." % max(a.gpus, world), file=sys.stderr)
         return 2
 
-    import numpy as np
     import torch
     import synth
     from paper_2212_12737_amd import ffk
@@ -135,87 +224,114 @@ def main(argv=None) -> int:
     ctx = ffk.create(0)
     R = torch.as_tensor(s.R, device="cuda")
     F = torch.as_tensor(s.flat_forces(), device="cuda")
-    S = ffk.descriptor_build(ctx, R, cfg.sigma)
-    v = torch.as_tensor(synth.random_vectors(S.n, 5), device="cuda")
-    fl = mvm_flops(cfg.N, cfg.D)
-    log("config", cfg.name, "N", cfg.N, "M", cfg.M, "D", cfg.D, "n", S.n)
+    n = R.numel()
+    log("workload %s: M=%d N=%d D=%d n=%d k=%d lambda=%g strategy=%s"
+        % (cfg.name, cfg.M, cfg.N, cfg.D, n, cfg.k, cfg.lam, cfg.strategy))
 
-    rates = {}
-    for prec in ("bf16x3", "bf16", "fp32", "fp64"):
-        ms = time_mvm(ffk, ctx, S, v, ffk.PRECISIONS[prec], max(5, a.steps // 10), 3)
-        rates[prec] = {"ms": ms, "tflops": fl / ms / 1e9, "frac_peak": fl / ms / 1e9 / PEAK_TFLOPS[prec]}
-        log("mvm", prec, "%.4f ms  %.2f TFLOP/s" % (ms, rates[prec]["tflops"]))
+    if a.kernels_only:
+        x = torch.empty(1 << 27, dtype=torch.float64, device="cuda").normal_()
+        y = torch.empty_like(x)
+        y.copy_(x)                           # calibration: 1 GiB read + 1 GiB written
+        torch.cuda.synchronize()
+        S = ffk.descriptor_build(ctx, R, cfg.sigma)
+        idx = ffk.nystrom_select(ctx, S, cfg.strategy, cfg.k, lam=cfg.lam, seed=cfg.sel_seed)
+        P = ffk.precond_build(ctx, S, idx, cfg.lam, store=ffk.FP32)
+        v = torch.as_tensor(synth.random_vectors(n, 5), device="cuda")
+        for _ in range(a.kernels_only):
+            ffk.precond_apply(ctx, P, v)
+            ffk.kernel_mvm(ctx, S, v, prec=ffk.BF16X3)
+        torch.cuda.synchronize()
+        log("kernels-only done: %d applies and products, k_eff %d" % (a.kernels_only, P.k_eff))
+        return 0
 
-    # timed steps: the mixed solver's product
-    main_prec = ffk.BF16X3
     for _ in range(a.warmup):
-        ffk.kernel_mvm(ctx, S, v, prec=main_prec)
+        _, rec = solve(ffk, ctx, R, F, cfg, "mixed")
+        log("warmup solve", json.dumps(rec))
+    ffk.clock_enable(ctx, CLOCK_STRIDE)
+    recs = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(a.steps):
-        ffk.kernel_mvm(ctx, S, v, prec=main_prec)
+        alpha, rec = solve(ffk, ctx, R, F, cfg, "mixed")
+        recs.append(rec)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    ms_step = wall * 1e3 / a.steps
-    value = fl * a.steps / wall / 1e12
-    log("timed", a.steps, "steps: %.4f ms/step, %.2f TFLOP/s" % (ms_step, value))
+    clocks = ffk.clock_read(ctx)
+    ffk.clock_enable(ctx, 0)
+    sec = wall / a.steps
+    for r in recs:
+        log("timed solve", json.dumps(r))
+    log("timed: %d solves, %.3f s per solve" % (a.steps, sec))
+    ok_all = all(r["status"] == 0 and r["rel_res_true"] <= TOL for r in recs)
 
-    phases = ffk.kernel_mvm_phases(ctx, S, v, prec=main_prec, iters=max(5, min(a.steps, 50)))
-    model = phase_model(cfg.N, cfg.M, cfg.D, "bf16x3")
-    dom = max(phases, key=phases.get)
-    bound, amount, unit = model[dom]
+    # roofline entry: the clocked kernel with the most time in the timed solves
+    keff = recs[-1]["k_eff"]
+    clock_ms = {k: {"total_ms": t, "launches": c, "avg_ms": (t / c if c else None)} for k, (t, c) in clocks.items()}
+    log("kernel clocks:", json.dumps({k: (round(v["total_ms"], 2), v["launches"]) for k, v in clock_ms.items()}))
+    modelled = [k for k in clock_ms if kernel_model(k, cfg.N, cfg.D, n, keff, 4) and clock_ms[k]["launches"]]
+    dom = max(modelled, key=lambda k: clock_ms[k]["total_ms"])
+    bound, amount, unit = kernel_model(dom, cfg.N, cfg.D, n, keff, 4)
+    avg_s = clock_ms[dom]["avg_ms"] * 1e-3
+    traffic = measured_traffic(dom, cfg.name)
     if bound == "mfma":
-        ach = amount / (phases[dom] * 1e-3) / 1e12
-        roof = {"kernel": dom, "bound": "mfma", "achieved": ach, "peak": PEAK_TFLOPS["bf16x3"], "unit": "TFLOP/s",
-                "frac": ach / PEAK_TFLOPS["bf16x3"], "traffic": None}
+        ach = amount / avg_s / 1e12
+        roof = {"kernel": dom, "bound": "mfma", "achieved": ach, "peak": PEAK_TFLOPS["bf16"], "unit": "TFLOP/s",
+                "frac": ach / PEAK_TFLOPS["bf16"], "traffic": traffic}
     else:
-        ach = amount / (phases[dom] * 1e-3) / 1e9
+        ach = amount / avg_s / 1e9
         roof = {"kernel": dom, "bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": ach / PEAK_HBM_GBS, "traffic": None}
-    log("phases (ms):", json.dumps({k: round(x, 5) for k, x in phases.items()}), "dominant", dom)
+                "frac": ach / PEAK_HBM_GBS, "traffic": traffic}
+    roof.update({"avg_launch_ms": clock_ms[dom]["avg_ms"], "launches": clock_ms[dom]["launches"],
+                 "algorithmic_per_launch": amount, "algorithmic_unit": unit})
+    log("roofline:", json.dumps(roof))
 
-    extra = {}
-    for c in [c for c in a.extra_configs.split(",") if c]:
+    arms = {"mixed": recs[-1]}
+    if not a.no_fp64:
+        _, arms["fp64"] = solve(ffk, ctx, R, F, cfg, "fp64")
+        log("fp64 solve", json.dumps(arms["fp64"]))
+        _, arms["mixed_fp32"] = solve(ffk, ctx, R, F, cfg, "mixed_fp32")
+        log("mixed fp32 solve", json.dumps(arms["mixed_fp32"]))
+
+    S = ffk.descriptor_build(ctx, R, cfg.sigma)
+    v = torch.as_tensor(synth.random_vectors(n, 5), device="cuda")
+    rates = {cfg.name: mvm_rates(ffk, ctx, cfg, S, v, a.mvm_steps, 3)}
+    del S
+    for c in [c for c in a.mvm_configs.split(",") if c]:
         cc = synth.CONFIGS[c]
         sc = synth.config_system(cc)
         Sc = ffk.descriptor_build(ctx, torch.as_tensor(sc.R, device="cuda"), cc.sigma)
         vc = torch.as_tensor(synth.random_vectors(Sc.n, 5), device="cuda")
-        flc = mvm_flops(cc.N, cc.D)
-        extra[c] = {}
-        for prec in ("bf16x3", "bf16", "fp32", "fp64"):
-            ms = time_mvm(ffk, ctx, Sc, vc, ffk.PRECISIONS[prec], 5, 2)
-            extra[c][prec] = {"ms": ms, "tflops": flc / ms / 1e9, "frac_peak": flc / ms / 1e9 / PEAK_TFLOPS[prec]}
-            log("mvm", c, prec, "%.3f ms %.1f TFLOP/s" % (ms, flc / ms / 1e9))
-        del Sc
+        rates[c] = mvm_rates(ffk, ctx, cc, Sc, vc, max(5, a.mvm_steps // 4), 2)
+        rates[c]["shape"] = {"M": cc.M, "N": cc.N, "D": cc.D, "n": Sc.n}
+        del Sc, vc
 
-    pcg = None
-    if not a.no_pcg:
-        _, mixed = solve(ffk, ctx, S, F, cfg, True)
-        log("pcg mixed", json.dumps(mixed))
-        _, plain = solve(ffk, ctx, S, F, cfg, False)
-        log("pcg fp64", json.dumps(plain))
-        pcg = {"mixed": mixed, "fp64": plain, "speedup_total": plain["t_total_s"] / mixed["t_total_s"],
-               "speedup_pcg": plain["t_pcg_s"] / mixed["t_pcg_s"], "tol": 1e-6}
+    cpu = None
+    if not a.no_cpu:
+        iters = arms["fp64"]["iters"] if "fp64" in arms else recs[-1]["iters"]
+        cpu = cpu_baseline(cfg, s, iters, keff)
+        log("cpu oracle:", json.dumps(cpu))
 
-    cpu = None if a.no_cpu else cpu_baseline(cfg, s)
     out = {
         "metric": "kernel-MVM TFLOP/s; PCG time to 1e-6 residual, mixed+learned vs plain FP64",
-        "value": value, "unit": "TFLOP/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
-        "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "bf16x3", "data": "synthetic",
-        "config": {"workload": "%s: M=%d atoms, N=%d geometries, n=%d, D=%d, kernel product in split BF16 on MFMA"
-                               % (cfg.name, cfg.M, cfg.N, S.n, cfg.D),
-                   "M": cfg.M, "N": cfg.N, "n": S.n, "D": cfg.D, "lambda": cfg.lam, "k": cfg.k,
-                   "strategy": "pivchol", "parallelism": "single GPU"},
+        "value": sec, "unit": "s per solve to 1e-6 true relative residual (mixed precision)",
+        "n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "ms_per_step": sec * 1e3,
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16x3+fp64", "data": "synthetic",
+        "config": {"workload": "%s: M=%d atoms, N=%d geometries, n=%d unknowns, D=%d, lambda=%g, k=%d %s Nystroem, "
+                               "full solve (descriptor, selection, preconditioner build, mixed PCG to 1e-6)"
+                               % (cfg.name, cfg.M, cfg.N, n, cfg.D, cfg.lam, cfg.k, cfg.strategy),
+                   "M": cfg.M, "N": cfg.N, "n": n, "D": cfg.D, "lambda": cfg.lam, "k": cfg.k,
+                   "strategy": cfg.strategy, "parallelism": "single GPU"},
+        "converged": ok_all,
         "roofline": roof,
-        "mvm_rates": rates,
-        "mvm_phases_ms": phases,
-        "pcg": pcg,
-        "extra_mvm": extra or None,
+        "kernel_clocks_ms": clock_ms,
+        "solves": arms,
+        "speedup_vs_fp64": (arms["fp64"]["t_total_s"] / sec) if "fp64" in arms else None,
+        "mvm_tflops": rates,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
-    return 0
+    return 0 if ok_all else 1
 
 
 if __name__ == "__main__":

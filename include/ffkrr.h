@@ -110,6 +110,29 @@ ffk_status ffk_kernel_mvm_phases(ffk_ctx* ctx, ffk_system* sys, const double* v_
                                  double shift, ffk_precision prec, int32_t iters,
                                  double* phase_ms_host, void* stream);
 
+/* Kernel clocks.  While enabled, the library records a HIP event pair on the
+ * launching stream around every `stride`-th launch of each kernel named
+ * below and adds the elapsed time to that kernel's clock; recording never
+ * waits for the GPU.  ffk_clock_enable synchronizes the device and zeroes
+ * every clock (stride = 0 stops recording, stride < 0 is FFK_ERR_ARG).
+ * ffk_clock_read synchronizes the device and returns the total milliseconds
+ * and the number of timed launches of clock `id`.  Process-wide, for the
+ * device that was current when enabled; not thread-safe. */
+typedef enum {
+  FFK_CLK_JV = 0,          /* U = J v (+ low-precision copies, column partials) */
+  FFK_CLK_COLSUM = 1,      /* column sums 1^T U */
+  FFK_CLK_GEMM1 = 2,       /* P = X_c U^T with the fused W / row-sum epilogue */
+  FFK_CLK_GEMM2 = 3,       /* [dA | -W] [U ; X_c] (split-K partials or G epilogue) */
+  FFK_CLK_GEMM2_REDUCE = 4,/* split-K reduction with the G epilogue */
+  FFK_CLK_JTG = 5,         /* y = J^T G + shift v */
+  FFK_CLK_GEMV_T = 6,      /* preconditioner apply: L^T r partials (one pass over L) */
+  FFK_CLK_GEMV_N = 7,      /* preconditioner apply: L t partials (one pass over L) */
+  FFK_CLK_CORE = 8,        /* preconditioner apply: the two k x k triangular products */
+  FFK_CLK_COUNT = 9
+} ffk_clock;
+ffk_status ffk_clock_enable(ffk_ctx* ctx, int32_t stride);
+ffk_status ffk_clock_read(ffk_ctx* ctx, int32_t id, double* total_ms_host, int64_t* launches_host);
+
 /* Force prediction F_test = K(test, train) alpha (section 2.1: predictions
  * cost linear in n_train).  test and train must have the same M and sigma.
  * alpha: 3 M N_train float64; F_test: 3 M N_test float64.  FP64. */

@@ -132,6 +132,24 @@ ffk_status ffk_kernel_mvm_phases(ffk_ctx* ctx, ffk_system* s, const double* v, d
   });
 }
 
+ffk_status ffk_clock_enable(ffk_ctx* ctx, int32_t stride) {
+  if (!ctx) return FFK_ERR_ARG;
+  return guarded(ctx, [&]() {
+    require(stride >= 0, "clock_enable: stride must be >= 0");
+    clock_enable(stride);
+    return FFK_OK;
+  });
+}
+
+ffk_status ffk_clock_read(ffk_ctx* ctx, int32_t id, double* total_ms, int64_t* launches) {
+  if (!ctx || !total_ms || !launches) return FFK_ERR_ARG;
+  return guarded(ctx, [&]() {
+    require(id >= 0 && id < FFK_CLK_COUNT, "clock_read: unknown clock id");
+    clock_read(id, total_ms, launches);
+    return FFK_OK;
+  });
+}
+
 ffk_status ffk_kernel_predict(ffk_ctx* ctx, const ffk_system* train, const ffk_system* test, const double* alpha,
                               double* F, void* stream) {
   if (!ctx || !train || !test) return FFK_ERR_ARG;

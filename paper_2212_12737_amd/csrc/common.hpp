@@ -286,6 +286,16 @@ void mlp_prepare_inputs(const ffk_mlp* net, const ffk_system* s, float* out, int
 void mlp_fit_norm(ffk_mlp* net, const float* X, int64_t B, hipStream_t st);
 void block_log_scores(const double* tau, int64_t N, int M, float* y, hipStream_t st);
 
+// clock.cpp -- per-kernel event clocks (ids match ffk_clock in ffkrr.h)
+enum ClockId {
+  CLK_JV = 0, CLK_COLSUM, CLK_GEMM1, CLK_GEMM2, CLK_GEMM2_REDUCE, CLK_JTG,
+  CLK_GEMV_T, CLK_GEMV_N, CLK_CORE, CLK_COUNT
+};
+void clk_begin(int id, hipStream_t st);
+void clk_end(int id, hipStream_t st);
+void clock_enable(int stride);
+void clock_read(int id, double* total_ms, int64_t* launches);
+
 // rng shared by host and device code of the library
 __host__ __device__ inline uint64_t splitmix64_at(uint64_t seed, uint64_t counter) {
   uint64_t z = seed + (counter + 1ull) * 0x9E3779B97F4A7C15ull;

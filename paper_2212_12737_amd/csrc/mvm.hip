@@ -359,8 +359,10 @@ static void mvm_gemms_scalar(const MvmArgs& a, const T* Xt, const T* Xs, const T
     g.nseg = 1;
     g.seg[0] = SegS<T>{Xt, D, 1, U, D, 1, (int)D};
     EpiW<T, 128> e{Bc, Ns, a.pd, Wn, Ns, a.wpart, ntn, Nt, Ns};
+    clk_begin(CLK_GEMM1, st);
     gemm_scalar_kernel<T, 128, 128, 16, true, true, EpiW<T, 128>><<<dim3(ntn, cdiv(Nt, 128)), 256, 0, st>>>(g, e);
     LAUNCHCHK();
+    clk_end(CLK_GEMM1, st);
   }
   mark(ev, 3, st);
   ScalarArgs<T> g{};
@@ -374,14 +376,20 @@ static void mvm_gemms_scalar(const MvmArgs& a, const T* Xt, const T* Xs, const T
   while (splits > 1 && (size_t)splits * Nt * D * sizeof(T) > a.part_bytes) splits >>= 1;
   if (splits == 1) {
     EpiG<128> e{a.s, a.Xt64, D, a.wpart, ntn, a.a0, a.G, D, Nt, (int)D};
+    clk_begin(CLK_GEMM2, st);
     gemm_scalar_kernel<T, 128, 128, 16, true, false, EpiG<128>><<<dim3(cdiv(D, 128), cdiv(Nt, 128)), 256, 0, st>>>(g, e);
     LAUNCHCHK();
+    clk_end(CLK_GEMM2, st);
   } else {
     EpiPart<T> e{static_cast<T*>(a.part), D, Nt, (int)D};
+    clk_begin(CLK_GEMM2, st);
     gemm_scalar_kernel<T, 128, 128, 16, true, false, EpiPart<T>><<<dim3(cdiv(D, 128), cdiv(Nt, 128), splits), 256, 0, st>>>(g, e);
     LAUNCHCHK();
+    clk_end(CLK_GEMM2, st);
+    clk_begin(CLK_GEMM2_REDUCE, st);
     k_g_reduce<T><<<Nt, 256, 0, st>>>(static_cast<const T*>(a.part), splits, Nt, D, a.s, a.Xt64, a.wpart, ntn, a.a0, a.G);
     LAUNCHCHK();
+    clk_end(CLK_GEMM2_REDUCE, st);
   }
 }
 
@@ -397,8 +405,10 @@ static void mvm_gemms_bf16(ffk_system* s, int prec, const MvmArgs& a, hipStream_
     g.nseg = 1;
     g.seg[0] = SegB{s->Xch.as<bf16_t>(), s->Xcl.as<bf16_t>(), w.Uh.as<bf16_t>(), w.Ul.as<bf16_t>(), Dk, Dk, (int)Dk};
     EpiWbf<128, X3> e{cs.B.as<float>(), Nr, a.pd, w.Wnh.as<bf16_t>(), w.Wnl.as<bf16_t>(), a.wpart, ntn, (int)N};
+    clk_begin(CLK_GEMM1, st);
     gemm_bf16_dma_kernel<128, 128, 4, X3, EpiWbf<128, X3>><<<dim3(ntn, ntn), 256, 0, st>>>(g, e);
     LAUNCHCHK();
+    clk_end(CLK_GEMM1, st);
   }
   mark(ev, 3, st);
   Bf16Args g{};
@@ -410,15 +420,21 @@ static void mvm_gemms_bf16(ffk_system* s, int prec, const MvmArgs& a, hipStream_
   while (splits > 1 && (size_t)splits * N * D * sizeof(float) > a.part_bytes) splits >>= 1;
   if (splits == 1) {
     EpiG<128> e{a.s, a.Xt64, D, a.wpart, ntn, a.a0, a.G, D, (int)N, (int)D};
+    clk_begin(CLK_GEMM2, st);
     gemm_bf16_dma_kernel<128, 128, 4, X3, EpiG<128>><<<dim3(Dr / 128, ntn), 256, 0, st>>>(g, e);
     LAUNCHCHK();
+    clk_end(CLK_GEMM2, st);
   } else {
     EpiPart<float> e{static_cast<float*>(a.part), D, (int)N, (int)D};
+    clk_begin(CLK_GEMM2, st);
     gemm_bf16_dma_kernel<128, 128, 4, X3, EpiPart<float>><<<dim3(Dr / 128, ntn, splits), 256, 0, st>>>(g, e);
     LAUNCHCHK();
+    clk_end(CLK_GEMM2, st);
+    clk_begin(CLK_GEMM2_REDUCE, st);
     k_g_reduce<float><<<N, 256, 0, st>>>(static_cast<const float*>(a.part), splits, N, D, a.s, a.Xt64, a.wpart, ntn,
                                          a.a0, a.G);
     LAUNCHCHK();
+    clk_end(CLK_GEMM2_REDUCE, st);
   }
 }
 
@@ -475,6 +491,7 @@ void kernel_mvm_ev(ffk_system* s, const double* v, double* y, double shift, int 
   const size_t shm = (size_t)2 * GT * 3 * M * sizeof(double);
   double* pd = w.pd.as<double>();
   double* cp = w.spart.as<double>();
+  clk_begin(CLK_JV, st);
   if (prec == FFK_FP64)
     k_jv_tile<true, false, false><<<nblk, 256, shm, st>>>(s->R.as<double>(), s->pairs.as<int>(), v, s->Xc.as<double>(),
                                                           N, M, D, w.U64.as<double>(), nullptr, nullptr, nullptr, 0,
@@ -489,9 +506,12 @@ void kernel_mvm_ev(ffk_system* s, const double* v, double* y, double shift, int 
                                                           w.Ul.as<bf16_t>(), ldu, w.UTh.as<bf16_t>(),
                                                           w.UTl.as<bf16_t>(), Nr, pd, cp);
   LAUNCHCHK();
+  clk_end(CLK_JV, st);
   mark(ev, 1, st);
+  clk_begin(CLK_COLSUM, st);
   k_colsum_final<<<cdiv(D, 64), 256, 0, st>>>(cp, nblk, D, w.s.as<double>());
   LAUNCHCHK();
+  clk_end(CLK_COLSUM, st);
   mark(ev, 2, st);
   MvmArgs a{N, N, D, s->a0, s->Xc.as<double>(), pd, w.s.as<double>(), w.wpart.as<double>(), w.G.as<double>(),
             w.part.get(), w.part.bytes()};
@@ -510,8 +530,10 @@ void kernel_mvm_ev(ffk_system* s, const double* v, double* y, double shift, int 
   (void)bf;
   mark(ev, 4, st);
   const int tb = M <= 64 ? 64 : 128;
+  clk_begin(CLK_JTG, st);
   k_jtg<<<N, tb, (3 * M + D) * sizeof(double), st>>>(s->R.as<double>(), w.G.as<double>(), v, shift, M, D, y);
   LAUNCHCHK();
+  clk_end(CLK_JTG, st);
   mark(ev, 5, st);
 }
 
@@ -573,8 +595,10 @@ void kernel_predict(const ffk_system* tr, const ffk_system* te, const double* al
       tr->R.as<double>(), tr->pairs.as<int>(), alpha, tr->Xc.as<double>(), Ns, M, D, U.as<double>(), nullptr, nullptr,
       nullptr, 0, nullptr, nullptr, 0, pd.as<double>(), cpart.as<double>());
   LAUNCHCHK();
+  clk_begin(CLK_COLSUM, st);
   k_colsum_final<<<cdiv(D, 64), 256, 0, st>>>(cpart.as<double>(), nblk, D, sv.as<double>());
   LAUNCHCHK();
+  clk_end(CLK_COLSUM, st);
   k_center_with<<<Nt, 256, 0, st>>>(te->X.as<double>(), tr->xmean.as<double>(), D, Xt.as<double>(), sqt.as<double>());
   LAUNCHCHK();
   {
@@ -593,8 +617,10 @@ void kernel_predict(const ffk_system* tr, const ffk_system* te, const double* al
   mvm_gemms_scalar<double>(a, Xt.as<double>(), tr->Xc.as<double>(), U.as<double>(), dA.as<double>(), B.as<double>(),
                            Wn.as<double>(), st, nullptr);
   const int tb = M <= 64 ? 64 : 128;
+  clk_begin(CLK_JTG, st);
   k_jtg<<<Nt, tb, (3 * M + D) * sizeof(double), st>>>(te->R.as<double>(), G.as<double>(), nullptr, 0.0, M, D, F);
   LAUNCHCHK();
+  clk_end(CLK_JTG, st);
   HIPCHK(hipStreamSynchronize(st));   // temporaries are freed on return
 }
 

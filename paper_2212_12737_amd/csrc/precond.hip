@@ -402,21 +402,25 @@ __global__ void k_finish_n(const double* __restrict__ part, int nb, int64_t stri
 
 template <typename TA>
 static void gemv_t(const TA* A, int64_t nrow, int64_t lda, int64_t ncol, const double* x, double* y, int tri,
-                   double* part, hipStream_t st) {
+                   double* part, hipStream_t st, int clk = -1) {
   const int nb = cdiv(nrow, TR_ROWS);
+  if (clk >= 0) clk_begin(clk, st);
   k_gemvt_part<TA><<<dim3(cdiv(ncol, TR_COLS), nb), 256, 0, st>>>(A, nrow, lda, ncol, x, part, tri);
   LAUNCHCHK();
+  if (clk >= 0) clk_end(clk, st);
   k_sum_rows<<<cdiv(ncol, 256), 256, 0, st>>>(part, nb, ncol, y);
   LAUNCHCHK();
 }
 
 template <typename TA>
 static void gemv_n(const TA* A, int64_t nrow, int64_t lda, int64_t ncol, const double* t, const double* r,
-                   double alpha, double* out, int tri, double* part, hipStream_t st) {
+                   double alpha, double* out, int tri, double* part, hipStream_t st, int clk = -1) {
   const int nb = cdiv(ncol, DN_COLS);
   const int gx = cdiv(nrow, DN_ROWS);
+  if (clk >= 0) clk_begin(clk, st);
   k_gemvn_part<TA><<<dim3(gx, nb), 256, 0, st>>>(A, nrow, lda, ncol, t, part, tri);
   LAUNCHCHK();
+  if (clk >= 0) clk_end(clk, st);
   k_finish_n<<<cdiv(nrow, 256), 256, 0, st>>>(part, nb, (int64_t)gx * DN_ROWS, nrow, r, alpha, out);
   LAUNCHCHK();
 }
@@ -427,10 +431,12 @@ static void apply_t(const ffk_precond* P, const double* r, double* z, hipStream_
   const int64_t n = P->n, k = P->k_eff;
   const double* F = P->Finv.as<double>();
   double* part = P->work.as<double>();
-  gemv_t<TA>(L, n, P->ld, k, r, P->y.as<double>(), 0, part, st);
+  gemv_t<TA>(L, n, P->ld, k, r, P->y.as<double>(), 0, part, st, CLK_GEMV_T);
+  clk_begin(CLK_CORE, st);
   gemv_n<double>(F, k, P->ldf, k, P->y.as<double>(), nullptr, 1.0, P->t1.as<double>(), 1, part, st);
   gemv_t<double>(F, k, P->ldf, k, P->t1.as<double>(), P->t.as<double>(), 1, part, st);
-  gemv_n<TA>(L, n, P->ld, k, P->t.as<double>(), r, 1.0 / P->lambda, z, 0, part, st);
+  clk_end(CLK_CORE, st);
+  gemv_n<TA>(L, n, P->ld, k, P->t.as<double>(), r, 1.0 / P->lambda, z, 0, part, st, CLK_GEMV_N);
 }
 
 __global__ void k_scale(const double* r, double a, int64_t n, double* z) {

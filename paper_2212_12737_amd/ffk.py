@@ -63,6 +63,8 @@ _SIGS = {
     "ffk_descriptor_export": (I32, [P, P, P, P]),
     "ffk_kernel_mvm": (I32, [P, P, P, P, DBL, I32, P]),
     "ffk_kernel_mvm_phases": (I32, [P, P, P, P, DBL, I32, I32, ctypes.POINTER(DBL), P]),
+    "ffk_clock_enable": (I32, [P, I32]),
+    "ffk_clock_read": (I32, [P, I32, ctypes.POINTER(DBL), ctypes.POINTER(I64)]),
     "ffk_kernel_predict": (I32, [P, P, P, P, P, P]),
     "ffk_kernel_columns": (I32, [P, P, P, I64, P, P]),
     "ffk_kernel_diag": (I32, [P, P, P, P]),
@@ -203,6 +205,24 @@ def kernel_mvm_phases(ctx: Context, sys: System, v: torch.Tensor, prec: int = FP
     ctx.check(lib().ffk_kernel_mvm_phases(ctx.h, sys.h, _ptr(v, torch.float64), _ptr(y), shift, prec, iters, ms,
                                           _stream(stream)), "kernel_mvm_phases")
     return dict(zip(MVM_PHASES, list(ms)))
+
+
+CLOCKS = ("jv", "colsum", "gemm1", "gemm2", "gemm2_reduce", "jtg", "gemv_t", "gemv_n", "core")
+
+
+def clock_enable(ctx: Context, stride: int = 1) -> None:
+    """Zero the kernel clocks and time every stride-th launch (0 stops recording)."""
+    ctx.check(lib().ffk_clock_enable(ctx.h, int(stride)), "clock_enable")
+
+
+def clock_read(ctx: Context) -> dict:
+    """{kernel: (total_ms, timed launches)} for every clock; synchronizes the device."""
+    out = {}
+    for i, name in enumerate(CLOCKS):
+        ms, cnt = DBL(0.0), I64(0)
+        ctx.check(lib().ffk_clock_read(ctx.h, i, ctypes.byref(ms), ctypes.byref(cnt)), "clock_read")
+        out[name] = (ms.value, cnt.value)
+    return out
 
 
 def kernel_predict(ctx: Context, train: System, test: System, alpha: torch.Tensor, stream=None) -> torch.Tensor:
