@@ -1,7 +1,7 @@
 #!/usr/bin/env python3
 """Benchmark of the hot path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config C2] [--mvm-configs C5]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config m21_n2000] [--mvm-configs m60_n20000]
 
 Workload (default): M = 21 atoms, N = 2000 geometries (n = 126000 unknowns,
 D = 210 inverse distances), Matern-5/2 sigma = 10, lambda = 1e-9, Nystroem
@@ -200,8 +200,8 @@ def main(argv=None) -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3, help="timed solves")
     ap.add_argument("--warmup", type=int, default=1, help="untimed solves before the timed ones")
-    ap.add_argument("--config", default="C2")
-    ap.add_argument("--mvm-configs", default="C5", help="comma list of further systems for kernel-product rates")
+    ap.add_argument("--config", default="m21_n2000")
+    ap.add_argument("--mvm-configs", default="m60_n20000", help="comma list of further systems for kernel-product rates")
     ap.add_argument("--mvm-steps", type=int, default=20)
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison solve")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle sample")

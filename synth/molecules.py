@@ -61,20 +61,22 @@ def _cfg(c: int, **kw) -> Config:
                   sel_seed=1000 * c + 3, **kw)
 
 
-# The five workloads: small plain-FP64 case, the mixed-precision cases and the
-# learned-selection case.  lambda is 1e-9 where the workload does not state it.
+# The five workloads, keyed by atoms and geometries: the small plain-FP64 case
+# (uniform selection), the mixed-precision cases (pivoted Cholesky, leverage),
+# the learned-selection case and the large single-GPU case.  lambda is 1e-9
+# where the workload does not state it.  Seeds derive from the workload index.
 CONFIGS = {
-    "C1": _cfg(1, name="C1", M=9, N=200, sd=0.05, coulomb=False, k=100, lam=1e-8,
+    "m9_n200": _cfg(1, name="m9_n200", M=9, N=200, sd=0.05, coulomb=False, k=100, lam=1e-8,
                strategy="uniform"),
-    "C2": _cfg(2, name="C2", M=21, N=2000, sd=0.08, coulomb=True, k=2000, lam=1e-9,
+    "m21_n2000": _cfg(2, name="m21_n2000", M=21, N=2000, sd=0.08, coulomb=True, k=2000, lam=1e-9,
                strategy="pivchol"),
-    "C3": _cfg(3, name="C3", M=42, N=5000, sd=0.08, coulomb=True, k=5000, lam=1e-9,
+    "m42_n5000": _cfg(3, name="m42_n5000", M=42, N=5000, sd=0.08, coulomb=True, k=5000, lam=1e-9,
                strategy="leverage"),
-    "C4": _cfg(4, name="C4", M=21, N=10000, sd=0.08, coulomb=True, k=4000, lam=1e-9,
+    "m21_n10000": _cfg(4, name="m21_n10000", M=21, N=10000, sd=0.08, coulomb=True, k=4000, lam=1e-9,
                strategy="learned",
                extra={"train_systems": 20, "train_N": 2000, "train_disp_seed0": 4100,
                       "test_disp_seed": 4200}),
-    "C5": _cfg(5, name="C5", M=60, N=20000, sd=0.08, coulomb=True, k=8000, lam=1e-9,
+    "m60_n20000": _cfg(5, name="m60_n20000", M=60, N=20000, sd=0.08, coulomb=True, k=8000, lam=1e-9,
                strategy="learned"),
 }
 

@@ -92,7 +92,7 @@ def test_mvm_fp64_matches_oracle(ffk, ctx, M, N):
 
 def test_mvm_fp64_forces_label_vector(ffk, ctx):
     """The product with the label vector (F is orthogonal to the rigid-motion null space)."""
-    s = synth.config_system(synth.CONFIGS["C1"])
+    s = synth.config_system(synth.CONFIGS["m9_n200"])
     S = ffk.descriptor_build(ctx, dev(s.R), SIGMA)
     F = s.flat_forces()
     y = host(ffk.kernel_mvm(ctx, S, dev(F)))
@@ -247,8 +247,8 @@ def test_plain_cg_matches_cholesky(ffk, ctx):
 
 
 @pytest.fixture(scope="module")
-def c1(ffk, ctx):
-    cfg = synth.CONFIGS["C1"]
+def small(ffk, ctx):
+    cfg = synth.CONFIGS["m9_n200"]
     s = synth.config_system(cfg)
     S = ffk.descriptor_build(ctx, dev(s.R), cfg.sigma)
     K = ok.dense_kernel(s.R, cfg.sigma)
@@ -260,13 +260,13 @@ def oracle_relres(K, lam, a, F):
     return np.linalg.norm(K @ a + lam * a - F) / np.linalg.norm(F)
 
 
-def test_pcg_c1_fp64_uniform(ffk, ctx, c1):
-    cfg, s, S, K, idx = c1
+def test_pcg_m9_n200_fp64_uniform(ffk, ctx, small):
+    cfg, s, S, K, idx = small
     assert host(idx).tolist() == osel.select_uniform(S.n, cfg.k, cfg.sel_seed).tolist()
     P = ffk.precond_build(ctx, S, idx, cfg.lam)
     F = s.flat_forces()
     a, rep = ffk.pcg_solve(ctx, S, P, dev(F), cfg.lam, tol=1e-6, prec=ffk.FP64)
-    print("C1 fp64 iters", rep.iters, rep.rel_res_true, flush=True)
+    print("m9_n200 fp64 iters", rep.iters, rep.rel_res_true, flush=True)
     assert rep.status == 0
     assert oracle_relres(K, cfg.lam, host(a), F) <= 1.01e-6
     ref = osv.cholesky_solve(K, cfg.lam, F)
@@ -278,13 +278,13 @@ def test_pcg_c1_fp64_uniform(ffk, ctx, c1):
 
 
 @pytest.mark.parametrize("prec", ["bf16x3", "fp32", "bf16"])
-def test_pcg_c1_mixed_precision_reaches_fp64_residual(ffk, ctx, c1, prec):
-    cfg, s, S, K, idx = c1
+def test_pcg_m9_n200_mixed_precision_reaches_fp64_residual(ffk, ctx, small, prec):
+    cfg, s, S, K, idx = small
     P = ffk.precond_build(ctx, S, idx, cfg.lam, store=ffk.FP32)
     F = s.flat_forces()
     a, rep = ffk.pcg_solve(ctx, S, P, dev(F), cfg.lam, tol=1e-6, prec=ffk.PRECISIONS[prec], refresh_every=10,
                            escalate=True, max_iter=20000)
-    print("C1", prec, "iters", rep.iters, "esc", rep.n_escalations, "final", rep.final_prec, rep.rel_res_true,
+    print("m9_n200", prec, "iters", rep.iters, "esc", rep.n_escalations, "final", rep.final_prec, rep.rel_res_true,
           flush=True)
     assert rep.status == 0
     assert oracle_relres(K, cfg.lam, host(a), F) <= 1.01e-6

@@ -1,8 +1,7 @@
-"""Pins of the oracle MLP (learned column selection) and rule of thumb."""
+"""Pins of the oracle MLP (learned column selection)."""
 import numpy as np
 
 from oracle import mlp
-from oracle import rot
 
 
 def _setup(D=7, H=5, B=11, seed=0):
@@ -39,18 +38,3 @@ def test_adam_first_step_is_signed_lr():
     g = np.array([0.3, -2.0, 1e-3])
     th, m, v = mlp.adam_step(np.zeros(3), g, np.zeros(3), np.zeros(3), 1, lr=0.01)
     np.testing.assert_allclose(th, -0.01 * np.sign(g), rtol=1e-4)
-
-
-def test_rule_of_thumb_is_the_minimiser():
-    for n, kmin, m in [(63000, 100, 1.0), (500000, 236, 1.14), (31400, 10, 0.87)]:
-        ks = np.exp(np.linspace(np.log(1), np.log(n), 200001))
-        kbest = ks[np.argmin(rot.runtime_model(ks, n, kmin, m))]
-        assert abs(rot.k_rule_of_thumb(n, kmin, m) / kbest - 1) < 1e-3
-
-
-def test_power_law_fit_recovers_parameters():
-    n = 30000
-    k = np.array([100, 200, 400, 800, 1600])
-    iters = n * (150.0 / k) ** 1.1
-    kmin, m = rot.fit_power_law(k, iters, n)
-    assert abs(kmin - 150) < 1e-6 and abs(m - 1.1) < 1e-9

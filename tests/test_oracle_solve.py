@@ -77,10 +77,10 @@ def test_nystrom_equals_incomplete_cholesky_with_same_columns(tiny):
 
 
 @pytest.mark.slow
-def test_c1_uniform_pcg_reaches_cholesky_solution():
+def test_m9_n200_uniform_pcg_reaches_cholesky_solution():
     """The small plain-FP64 workload: PCG with uniform Nystroem k=100 to 1e-6
     against the dense Cholesky solve (Table II compares the two solvers)."""
-    cfg = synth.CONFIGS["C1"]
+    cfg = synth.CONFIGS["m9_n200"]
     s = synth.config_system(cfg)
     K = ok.dense_kernel(s.R, cfg.sigma)
     y = s.flat_forces()

@@ -30,6 +30,6 @@ def test_forces_are_negative_energy_gradient():
 
 
 def test_zero_net_force_and_torque():
-    s = synth.config_system(synth.CONFIGS["C1"])
+    s = synth.config_system(synth.CONFIGS["m9_n200"])
     assert np.abs(s.F.sum(1)).max() < 1e-12
     assert np.abs(np.cross(s.R, s.F).sum(1)).max() < 1e-12
