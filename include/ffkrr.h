@@ -175,8 +175,10 @@ ffk_status ffk_nystrom_select(ffk_ctx* ctx, ffk_system* sys, ffk_select strategy
  * FP64 by column panels; a column whose remaining diagonal falls to
  * 1e-12 max(diag K) is dropped (returns FFK_WARN_RANK_DROPPED).  Then the k x k
  * core lambda I + L^T L is factored in FP64 and its triangular inverse kept.
- * store_L = FFK_FP64 or FFK_FP32 selects the storage of L (the core is always
- * built from the stored L, so P stays symmetric positive definite). */
+ * store_L = FFK_FP64, FFK_FP32 or FFK_BF16 selects the storage of L (rounded
+ * to nearest; the core is always built in FP64 from the stored L, so P stays
+ * symmetric positive definite and the apply is exact for the stored L).
+ * FFK_BF16X3 is FFK_ERR_ARG. */
 ffk_status ffk_precond_build(ffk_ctx* ctx, ffk_system* sys, const int64_t* idx_dev, int64_t k,
                              double lambda, ffk_precision store_L, ffk_precond** out, void* stream);
 void ffk_precond_free(ffk_precond* P);

@@ -10,10 +10,15 @@ TEST INFRASTRUCTURE ONLY (see the package docstring).
   woodbury        -- P^{-1} for P = L L^T + lambda I (Eq. 3) by the Woodbury
                      identity (Eq. 4), with the k x k core factored by Cholesky.
   nystrom_lowrank -- K_nk K_kk^{-1} K_nk^T (Eq. 5) formed directly.
+  stored_factor   -- L as kept in a reduced storage format (FP32, or BF16 =
+                     the upper 16 bits of an IEEE binary32 with round to
+                     nearest even), so the Woodbury apply of the stored
+                     operator can be formed here too.
 
 Pins (tests/test_oracle_solve.py): Woodbury against a dense inverse, PCG
 against the Cholesky solve at moderate condition number, the one-step
-convergence of a preconditioner that reproduces K exactly (appendix A.1).
+convergence of a preconditioner that reproduces K exactly (appendix A.1),
+the rounding of stored_factor on hand-picked ties and its error bound.
 """
 from __future__ import annotations
 
@@ -74,3 +79,21 @@ def nystrom_lowrank(K: np.ndarray, S) -> np.ndarray:
     """K_nk K_kk^{-1} K_nk^T for the column subset S (Eq. 5)."""
     C = K[:, S]
     return C @ np.linalg.solve(K[np.ix_(S, S)], C.T)
+
+
+def stored_factor(L: np.ndarray, fmt: str) -> np.ndarray:
+    """L rounded to the storage format and returned as float64.
+
+    fp64: unchanged.  fp32: round to nearest binary32.  bf16: round to nearest
+    binary32 first, then keep the upper 16 bits of the binary32 pattern,
+    rounding the dropped 16 bits to nearest with ties to an even result."""
+    if fmt == "fp64":
+        return L.copy()
+    f = np.ascontiguousarray(L, dtype=np.float32)
+    if fmt == "fp32":
+        return f.astype(np.float64)
+    assert fmt == "bf16"
+    u = f.view(np.uint32).astype(np.uint64)
+    lsb = (u >> 16) & 1
+    u = (u + 0x7FFF + lsb) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)

@@ -191,8 +191,7 @@ struct ffk_precond {
   double lambda = 0.0;
   int32_t store = FFK_FP64;
   ffk::DBuf L;              // n x k column-major (double or float)
-  ffk::DBuf Finv;           // k x k row-major lower-triangular inverse of chol(core)
-  ffk::DBuf FinvT;          // its transpose, row-major
+  ffk::DBuf Finv;           // k x k column-major lower-triangular inverse of F = chol(core)
   ffk::DBuf y, t1, t;       // k-vectors
   ffk::DBuf work;           // partial sums of the split GEMVs
   int64_t bytes = 0;

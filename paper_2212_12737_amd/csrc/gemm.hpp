@@ -84,6 +84,12 @@ template <typename TI> struct ScalarArgs {
 // ---------------------------------------------------------------------------
 // Scalar-operand MFMA engine (FP64 / FP32)
 // ---------------------------------------------------------------------------
+// Conversion of a stored operand element to the compute type; bf16_t is the
+// raw 16-bit pattern of a bfloat16, not an integer.
+template <typename T, typename TI> __device__ inline T to_compute(TI x) { return (T)x; }
+template <> __device__ inline double to_compute<double, bf16_t>(bf16_t x) { return (double)bf2f(x); }
+template <> __device__ inline float to_compute<float, bf16_t>(bf16_t x) { return bf2f(x); }
+
 template <typename T, int BM, int BN, int BK, bool AKC, bool BKC, class Epi, typename TI = T>
 __global__ __launch_bounds__(256) void gemm_scalar_kernel(ScalarArgs<TI> g, Epi epi) {
   constexpr int PAD = 16;
@@ -125,7 +131,7 @@ __global__ __launch_bounds__(256) void gemm_scalar_kernel(ScalarArgs<TI> g, Epi 
       const int mm = AKC ? e / BK : e % BM;
       const int kk = AKC ? e % BK : e / BM;
       const int m = m0 + mm, k = k0 + kk;
-      ra[i] = (m < g.M && k < Kl && !(tri && k > m)) ? (T)s.A[(int64_t)m * s.sa0 + (int64_t)k * s.sa1] : T(0);
+      ra[i] = (m < g.M && k < Kl && !(tri && k > m)) ? to_compute<T>(s.A[(int64_t)m * s.sa0 + (int64_t)k * s.sa1]) : T(0);
     }
 #pragma unroll
     for (int i = 0; i < EB; ++i) {
@@ -133,7 +139,7 @@ __global__ __launch_bounds__(256) void gemm_scalar_kernel(ScalarArgs<TI> g, Epi 
       const int nn = BKC ? e / BK : e % BN;
       const int kk = BKC ? e % BK : e / BN;
       const int n = n0 + nn, k = k0 + kk;
-      rb[i] = (n < g.N && k < Kl) ? (T)s.B[(int64_t)n * s.sb0 + (int64_t)k * s.sb1] : T(0);
+      rb[i] = (n < g.N && k < Kl) ? to_compute<T>(s.B[(int64_t)n * s.sb0 + (int64_t)k * s.sb1]) : T(0);
     }
   };
   auto store = [&](int buf) {

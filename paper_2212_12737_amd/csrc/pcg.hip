@@ -3,7 +3,8 @@
 // Standard PCG (Hestenes-Stiefel recurrences) with alpha_0 = 0.  All vectors
 // and CG scalars are FP64 on the device; scalars never leave it except the two
 // needed for the stopping test and breakdown check (|r|^2 and p^T A p), read
-// back once per iteration.  The kernel product inside the iteration can run in
+// back once per iteration while the GPU already works on the next direction.
+// The kernel product inside the iteration can run in
 // a reduced precision; then the true residual r = F - K_lambda alpha is
 // recomputed with the FP64 product every `refresh_every` iterations and
 // replaces the recursively updated one (residual replacement; p is kept), and
@@ -34,8 +35,9 @@ __global__ void k_axpy2(double* __restrict__ x, double* __restrict__ r, const do
   r[i] -= g * q[i];
 }
 
-__global__ void k_update_p(double* __restrict__ p, const double* __restrict__ z, const double* __restrict__ sc,
-                           int rho_old, int rho_new, int flexible, int64_t n) {
+// pn = z + beta p (out of place, so that a speculative update can be redone)
+__global__ void k_update_p(double* __restrict__ pn, const double* __restrict__ p, const double* __restrict__ z,
+                           const double* __restrict__ sc, int rho_old, int rho_new, int flexible, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   double beta;
@@ -45,7 +47,7 @@ __global__ void k_update_p(double* __restrict__ p, const double* __restrict__ z,
   } else {
     beta = sc[rho_new] / sc[rho_old];
   }
-  p[i] = z[i] + beta * p[i];
+  pn[i] = z[i] + beta * p[i];
 }
 
 __global__ void k_sub(const double* __restrict__ a, const double* __restrict__ b, double* __restrict__ c, int64_t n) {
@@ -99,16 +101,22 @@ ffk_status pcg_solve(ffk_system* s, const ffk_precond* P, const double* F, doubl
   const bool timing = o->timing != 0;
   double t_mvm = 0, t_prec = 0, t_vec = 0, t_ref = 0;
 
-  DBuf r(n * 8), z(n * 8), p(n * 8), q(n * 8), tmp(n * 8), best(n * 8), sc(NSC * 8), part(kRedParts * 8);
+  DBuf r(n * 8), z(n * 8), p(n * 8), p2(n * 8), q(n * 8), tmp(n * 8), best(n * 8), sc(NSC * 8), part(kRedParts * 8);
   double* R = r.as<double>();
   double* Z = z.as<double>();
   double* Pv = p.as<double>();
+  double* Pn = p2.as<double>();
   double* Q = q.as<double>();
   double* SC = sc.as<double>();
   double* PART = part.as<double>();
   const int nb = cdiv(n, 256);
   s->ctx->host_scratch.ensure(64);
   double* hs = s->ctx->host_scratch.as<double>();
+  struct Ev {
+    hipEvent_t e = nullptr;
+    ~Ev() { if (e) (void)hipEventDestroy(e); }
+  } done;
+  HIPCHK(hipEventCreateWithFlags(&done.e, hipEventDisableTiming));
 
   auto apply_prec = [&](const double* in, double* out) {
     Timer tm(timing, st, &t_prec);
@@ -169,6 +177,20 @@ ffk_status pcg_solve(ffk_system* s, const ffk_precond* P, const double* F, doubl
     since_best = 0;
     restart_direction();
   };
+  // Next direction from the current r: z = M^-1 r, rho_new = r^T z, pn = z + beta p.
+  auto next_direction = [&](int rho_new) {
+    apply_prec(R, Z);
+    Timer tm(timing, st, &t_vec);
+    dot64(R, Z, n, PART, SC + rho_new, st);
+    if (o->flexible) dot64(Z, Q, n, PART, SC + S_ZQ, st);
+    k_update_p<<<nb, 256, 0, st>>>(Pn, Pv, Z, SC, rho, rho_new, o->flexible, n);
+    LAUNCHCHK();
+  };
+  // The host reads |r|^2 and p^T q once per iteration.  Except on refresh
+  // iterations, the next direction is enqueued before that read, so the GPU
+  // keeps working while the host waits; if the read then calls for a
+  // breakdown restart or a residual replacement, the speculative direction is
+  // discarded (p is only replaced after the decision).
   while (status == FFK_NOT_CONVERGED && it < max_iter) {
     const int cur = hi_phase ? FFK_FP64 : prec;
     {
@@ -182,9 +204,17 @@ ffk_status pcg_solve(ffk_system* s, const ffk_precond* P, const double* F, doubl
       LAUNCHCHK();
       dot64(R, R, n, PART, SC + S_RR, st);
       HIPCHK(hipMemcpyAsync(hs, SC + S_PAP, 16, hipMemcpyDeviceToHost, st));
-      HIPCHK(hipStreamSynchronize(st));
+      HIPCHK(hipEventRecord(done.e, st));
     }
     ++it;
+    const int rho_new = rho ^ 1;
+    const bool periodic = refresh > 0 && (it % refresh) == 0 && cur != FFK_FP64;
+    bool have_next = false;
+    if (!periodic) {
+      next_direction(rho_new);
+      have_next = true;
+    }
+    HIPCHK(hipEventSynchronize(done.e));
     const double pap = hs[0], rr = hs[1];
     if (!(pap > 0.0) || !std::isfinite(pap) || !std::isfinite(rr)) {
       if (o->escalate && cur != FFK_FP64) {
@@ -201,7 +231,6 @@ ffk_status pcg_solve(ffk_system* s, const ffk_precond* P, const double* F, doubl
     }
     if (rep && rep->hist_host && hist_len < rep->hist_cap) rep->hist_host[hist_len++] = rel_upd;
     const bool candidate = rel_upd <= o->tol;
-    const bool periodic = refresh > 0 && (it % refresh) == 0 && cur != FFK_FP64;
     if (candidate || periodic) {
       const double tr = true_residual();
       ++n_ref;
@@ -222,16 +251,10 @@ ffk_status pcg_solve(ffk_system* s, const ffk_precond* P, const double* F, doubl
         escalate_now();
         continue;
       }
+      have_next = false;   // r was replaced: the direction must come from it
     }
-    const int rho_new = rho ^ 1;
-    {
-      apply_prec(R, Z);
-      Timer tm(timing, st, &t_vec);
-      dot64(R, Z, n, PART, SC + rho_new, st);
-      if (o->flexible) dot64(Z, Q, n, PART, SC + S_ZQ, st);
-      k_update_p<<<nb, 256, 0, st>>>(Pv, Z, SC, rho, rho_new, o->flexible, n);
-      LAUNCHCHK();
-    }
+    if (!have_next) next_direction(rho_new);
+    std::swap(Pv, Pn);
     rho = rho_new;
   }
   if (status == FFK_NOT_CONVERGED && it > 0) {

@@ -10,10 +10,13 @@
 // invert it, (4) multiply the panel by that inverse (an in-place MFMA GEMM),
 // (5) zero the rows of earlier pivots and set the exact pivot values, as
 // Algorithm 1 leaves them.
-// The core lambda I + L^T L is formed from the stored L (FP64 or FP32) in FP64,
-// factored, and its triangular inverse Finv kept, so that
-//   z = lambda^-1 (r - L Finv^T Finv L^T r).
-// L and Finv are column-major with leading dimensions padded to 64 elements
+// The core C = lambda I + L^T L is formed from the stored L (FP64, FP32 or BF16)
+// in FP64 and factored, C = F F^T, and the triangular inverse F^-1 is kept:
+// z = lambda^-1 (r - L F^-T F^-1 L^T r), two passes over L and two over the
+// triangle of F^-1.  (Multiplying out F^-T F^-1 into one dense inverse would
+// save a pass but applies far less accurately at small lambda: the solve
+// then needs half again as many iterations.)
+// L and F^-1 are column-major with leading dimensions padded to 64 elements
 // (zero padding), so the GEMVs of the apply use aligned 16-byte loads.
 #include "gemm.hpp"
 
@@ -155,6 +158,17 @@ __global__ void k_f64_to_f32(const double* a, float* b, int64_t n) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e < n) b[e] = (float)a[e];
 }
+__global__ void k_f64_to_bf16(const double* a, bf16_t* b, int64_t n) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n) b[e] = f2bf((float)a[e]);
+}
+// zero the strict upper triangle of a column-major k x k matrix (ld rows)
+__global__ void k_zero_upper(double* A, int64_t k, int64_t ld) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= ld * k) return;
+  const int64_t r = e % ld, c = e / ld;
+  if (r < c) A[e] = 0.0;
+}
 __global__ void k_add_diag(double* C, int64_t k, int64_t ld, double lam) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < k) C[i + i * ld] += lam;
@@ -189,9 +203,12 @@ static void gram_cols(const TI* L, int64_t n, int64_t ld, int64_t k, double* C, 
   LAUNCHCHK();
 }
 
+int64_t precond_work_doubles(int64_t n, int64_t ld, int64_t keff, int store);
+
 ffk_precond* precond_build(ffk_system* s, const int64_t* idx, int64_t k, double lambda, int store, bool* dropped_any,
                            hipStream_t st) {
-  require(store == FFK_FP64 || store == FFK_FP32, "precond_build: store_L must be FFK_FP64 or FFK_FP32");
+  require(store == FFK_FP64 || store == FFK_FP32 || store == FFK_BF16,
+          "precond_build: store_L must be FFK_FP64, FFK_FP32 or FFK_BF16");
   const int64_t n = s->n;
   const int64_t ld = pad64(n);
   std::unique_ptr<ffk_precond> P(new ffk_precond());
@@ -225,13 +242,20 @@ ffk_precond* precond_build(ffk_system* s, const int64_t* idx, int64_t k, double 
   if (store == FFK_FP64) {
     if (keff > 0) gram_cols<double>(L64.as<double>(), n, ld, keff, core.as<double>(), ldf, st);
     P->L = std::move(L64);
-  } else {
+  } else if (store == FFK_FP32) {
     P->L.alloc(ld * ke * 4);
     k_f64_to_f32<<<cdiv(ld * keff, 256), 256, 0, st>>>(L64.as<double>(), P->L.as<float>(), ld * keff);
     LAUNCHCHK();
     HIPCHK(hipStreamSynchronize(st));
     L64.release();
     if (keff > 0) gram_cols<float>(P->L.as<float>(), n, ld, keff, core.as<double>(), ldf, st);
+  } else {
+    P->L.alloc(ld * ke * 2);
+    k_f64_to_bf16<<<cdiv(ld * keff, 256), 256, 0, st>>>(L64.as<double>(), P->L.as<bf16_t>(), ld * keff);
+    LAUNCHCHK();
+    HIPCHK(hipStreamSynchronize(st));
+    L64.release();
+    if (keff > 0) gram_cols<bf16_t>(P->L.as<bf16_t>(), n, ld, keff, core.as<double>(), ldf, st);
   }
   if (keff > 0) {
     k_add_diag<<<cdiv(keff, 256), 256, 0, st>>>(core.as<double>(), keff, ldf, lambda);
@@ -239,16 +263,15 @@ ffk_precond* precond_build(ffk_system* s, const int64_t* idx, int64_t k, double 
     const int64_t bad = potrf_lower(core.as<double>(), keff, ldf, st);
     if (bad >= 0) fail(FFK_ERR_NOT_SPD, "precond_build: core lambda I + L^T L is not positive definite");
     trtri_lower(core.as<double>(), keff, ldf, st);
+    // keep F^-1 strictly lower-triangular: the apply skips the zero triangle
+    k_zero_upper<<<cdiv(ldf * keff, 256), 256, 0, st>>>(core.as<double>(), keff, ldf);
+    LAUNCHCHK();
   }
   P->Finv = std::move(core);
   P->y.alloc(ldf * 8);
   P->t1.alloc(ldf * 8);
   P->t.alloc(ldf * 8);
-  {
-    const int64_t wt = (int64_t)cdiv(ld, 2048) * ke;           // transposed-product partials
-    const int64_t wn = (int64_t)cdiv(ke, 64) * (ld + 1024);    // direct-product partials
-    P->work.alloc(std::max(wt, wn) * 8);
-  }
+  P->work.alloc(precond_work_doubles(n, ld, ke, store) * 8);
   P->bytes = (int64_t)(P->L.bytes() + P->Finv.bytes() + P->work.bytes() + 3 * ldf * 8);
   HIPCHK(hipStreamSynchronize(st));
   return P.release();
@@ -257,71 +280,121 @@ ffk_precond* precond_build(ffk_system* s, const int64_t* idx, int64_t k, double 
 // ----------------------------------------------------------------- apply ----
 // The four products of the apply are memory-bound GEMVs over column-major
 // matrices whose leading dimension is a multiple of 64 with zero padding.
-// Each lane streams 4 consecutive rows per 16-byte load (two loads for FP64),
-// and the work is split over a 2-D grid so that enough loads are in flight to
-// run at HBM rate; partial results are combined by a second small pass in a
-// fixed order (deterministic).
-template <typename TA> struct Row4;
-template <> struct Row4<float> {
-  __device__ static inline void load(const float* p, double (&v)[4]) {
-    const float4 a = *reinterpret_cast<const float4*>(p);
-    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+// Every lane issues 16-byte loads (2 doubles, 4 floats or 8 bfloat16 of one
+// column), all of a lane's loads for a tile of columns back to back, and
+// accumulates in FP64.  Partial results of the 2-D grid are combined by a
+// second small pass in a fixed order (deterministic).
+// 16 bytes of one column: V consecutive elements, loaded raw and expanded to
+// FP64 only when consumed (keeps the loads in flight cheap in registers).
+template <typename TA> struct Vec16;
+template <> struct Vec16<double> {
+  static constexpr int V = 2;
+  __device__ static inline void expand(const uint4& a, double (&v)[2]) {
+    v[0] = __hiloint2double((int)a.y, (int)a.x);
+    v[1] = __hiloint2double((int)a.w, (int)a.z);
   }
 };
-template <> struct Row4<double> {
-  __device__ static inline void load(const double* p, double (&v)[4]) {
-    const double2 a = *reinterpret_cast<const double2*>(p);
-    const double2 b = *reinterpret_cast<const double2*>(p + 2);
-    v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
+template <> struct Vec16<float> {
+  static constexpr int V = 4;
+  __device__ static inline void expand(const uint4& a, double (&v)[4]) {
+    v[0] = __uint_as_float(a.x); v[1] = __uint_as_float(a.y);
+    v[2] = __uint_as_float(a.z); v[3] = __uint_as_float(a.w);
   }
 };
-
-constexpr int TR_ROWS = 2048;   // rows per block, transposed product (8 loads per lane per column)
-constexpr int TR_COLS = 16;     // columns per block (4 per wave)
-constexpr int DN_ROWS = 1024;   // rows per block, direct product (one 4-row load per lane per column)
-constexpr int DN_COLS = 64;     // columns per block
-
-// part[blockIdx.y][c] = sum_{i in block rows} A[i + c lda] x[i]   (i >= c only when tri)
-template <typename TA>
-__global__ __launch_bounds__(256) void k_gemvt_part(const TA* __restrict__ A, int64_t nrow, int64_t lda, int64_t ncol,
-                                                    const double* __restrict__ x, double* __restrict__ part, int tri) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int64_t i0 = (int64_t)blockIdx.y * TR_ROWS + 4 * lane;
-  const int64_t c0 = (int64_t)blockIdx.x * TR_COLS + wave * 4;
-  double xr[TR_ROWS / 256][4];
-#pragma unroll
-  for (int q = 0; q < TR_ROWS / 256; ++q)
+template <> struct Vec16<bf16_t> {
+  static constexpr int V = 8;
+  __device__ static inline void expand(const uint4& a, double (&v)[8]) {
+    const unsigned w[4] = {a.x, a.y, a.z, a.w};
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-      const int64_t i = i0 + 256 * q + e;
-      xr[q][e] = i < nrow ? x[i] : 0.0;
+      v[2 * e] = (double)__uint_as_float(w[e] << 16);
+      v[2 * e + 1] = (double)__uint_as_float(w[e] & 0xFFFF0000u);
     }
+  }
+};
+// The matrices of the apply are streamed once per pass (L does not fit in
+// the last-level cache): non-temporal loads keep them from evicting the
+// vectors and run closer to the HBM rate.
+typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
+template <typename TA> __device__ inline uint4 load16(const TA* p) {
+  const u32x4_t v = __builtin_nontemporal_load(reinterpret_cast<const u32x4_t*>(p));
+  return make_uint4(v.x, v.y, v.z, v.w);
+}
+
+constexpr int LT_COLS = 16;    // columns per block of the transposed product
+constexpr int LN_COLS = 256;   // columns per block of the direct product
+constexpr int LN_UNROLL = 16;  // loads in flight per lane in the direct product
+static_assert(LN_COLS % LN_UNROLL == 0 && LN_COLS <= 256, "direct-product column tile");
+
+// Sum of v[0..C) over the 64 lanes of a wave, one column per lane group:
+// recursive halving (each exchange step hands half of the values to the
+// partner lane) followed by plain butterflies.  On return lane l holds, in
+// v[0], the wave total of column lt_col<C>(l).
+template <int C>
+__device__ inline void wave_reduce_cols(double (&v)[C], int lane) {
+  int h = C / 2;
 #pragma unroll
-  for (int cc = 0; cc < 4; ++cc) {
-    const int64_t c = c0 + cc;
-    if (c >= ncol) break;
-    const TA* col = A + c * lda;
-    double a0 = 0.0, a1 = 0.0;
+  for (int off = 32; off >= 64 / C; off >>= 1) {
+    const bool upper = (lane & off) != 0;
 #pragma unroll
-    for (int q = 0; q < TR_ROWS / 256; ++q) {
-      const int64_t i = i0 + 256 * q;
-      if (i < nrow) {
-        double v[4];
-        Row4<TA>::load(col + i, v);
-        if (tri) {
-#pragma unroll
-          for (int e = 0; e < 4; ++e)
-            if (i + e < c) v[e] = 0.0;
-        }
-        a0 += v[0] * xr[q][0] + v[1] * xr[q][1];
-        a1 += v[2] * xr[q][2] + v[3] * xr[q][3];
+    for (int j = 0; j < C / 2; ++j) {
+      if (j < h) {
+        const double send = upper ? v[j] : v[j + h];
+        const double keep = upper ? v[j + h] : v[j];
+        v[j] = keep + __shfl_xor(send, off);
       }
     }
-    double a = a0 + a1;
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o);
-    if (lane == 0) part[(int64_t)blockIdx.y * ncol + c] = a;
+    h >>= 1;
   }
+#pragma unroll
+  for (int off = 32 / C; off >= 1; off >>= 1) v[0] += __shfl_xor(v[0], off);
+}
+template <int C> __device__ inline int lt_col(int lane) {
+  int c = 0;
+#pragma unroll
+  for (int off = 32, bit = C / 2; off >= 64 / C; off >>= 1, bit >>= 1)
+    if (lane & off) c += bit;
+  return c;
+}
+
+// part[blockIdx.y][c] = sum over the block's rows i of A[i + c lda] x[i]
+// (only rows i >= c when TRI: A lower-triangular).  Block: 256 lanes x V rows,
+// C columns.
+template <typename TA, int C, bool TRI>
+__global__ __launch_bounds__(256) void k_lt_part(const TA* __restrict__ A, int64_t nrow, int64_t lda, int64_t ncol,
+                                                 const double* __restrict__ x, double* __restrict__ part) {
+  constexpr int V = Vec16<TA>::V;
+  __shared__ double red[4][C];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t i = (int64_t)blockIdx.y * (256 * V) + (int64_t)threadIdx.x * V;
+  const int64_t c0 = (int64_t)blockIdx.x * C;
+  double acc[C];
+#pragma unroll
+  for (int c = 0; c < C; ++c) acc[c] = 0.0;
+  if (i < nrow) {   // i + V <= lda: i is a multiple of V and lda of 64
+    double xr[V];
+#pragma unroll
+    for (int e = 0; e < V; ++e) xr[e] = (i + e < nrow) ? x[i + e] : 0.0;
+    uint4 a[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      const int64_t col = c0 + c;
+      a[c] = (col < ncol && !(TRI && i + V <= col)) ? load16(A + col * lda + i) : make_uint4(0, 0, 0, 0);
+    }
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      double v[V];
+      Vec16<TA>::expand(a[c], v);
+#pragma unroll
+      for (int e = 0; e < V; ++e) acc[c] += ((TRI && i + e < c0 + c) ? 0.0 : v[e]) * xr[e];
+    }
+  }
+  wave_reduce_cols<C>(acc, lane);
+  if ((lane & (64 / C - 1)) == 0) red[wave][lt_col<C>(lane)] = acc[0];
+  __syncthreads();
+  if (threadIdx.x < C && c0 + threadIdx.x < ncol)
+    part[(int64_t)blockIdx.y * ncol + c0 + threadIdx.x] =
+        (red[0][threadIdx.x] + red[1][threadIdx.x]) + (red[2][threadIdx.x] + red[3][threadIdx.x]);
 }
 
 // y[c] = sum_b part[b][c]
@@ -338,50 +411,49 @@ __global__ void k_sum_rows(const double* __restrict__ part, int nb, int64_t ncol
   y[c] = a0 + a1;
 }
 
-// part[blockIdx.y][i] = sum_{c in block columns} A[i + c lda] t[c]   (c <= i only when tri)
-template <typename TA>
-__global__ __launch_bounds__(256) void k_gemvn_part(const TA* __restrict__ A, int64_t nrow, int64_t lda, int64_t ncol,
-                                                    const double* __restrict__ t, double* __restrict__ part, int tri) {
-  __shared__ double ts[DN_COLS];
-  const int64_t c0 = (int64_t)blockIdx.y * DN_COLS;
-  const int nc = (int)(ncol - c0 < DN_COLS ? ncol - c0 : DN_COLS);
-  if (threadIdx.x < DN_COLS) ts[threadIdx.x] = threadIdx.x < nc ? t[c0 + threadIdx.x] : 0.0;
+// part[blockIdx.y][i] = sum over the block's columns c of A[i + c lda] t[c]
+// (only c <= i when TRI).  Block: 256 lanes x V rows, LN_COLS columns.
+template <typename TA, bool TRI>
+__global__ __launch_bounds__(256) void k_ln_part(const TA* __restrict__ A, int64_t nrow, int64_t lda, int64_t ncol,
+                                                 const double* __restrict__ t, double* __restrict__ part,
+                                                 int64_t stride) {
+  constexpr int V = Vec16<TA>::V;
+  __shared__ double ts[LN_COLS];
+  const int64_t c0 = (int64_t)blockIdx.y * LN_COLS;
+  const int nc = (int)(ncol - c0 < LN_COLS ? ncol - c0 : LN_COLS);
+  for (int c = threadIdx.x; c < LN_COLS; c += 256) ts[c] = c < nc ? t[c0 + c] : 0.0;
   __syncthreads();
-  const int64_t i = (int64_t)blockIdx.x * DN_ROWS + 4 * threadIdx.x;
+  const int64_t i = (int64_t)blockIdx.x * (256 * V) + (int64_t)threadIdx.x * V;
   if (i >= nrow) return;
-  double a[4] = {0.0, 0.0, 0.0, 0.0};
-  const TA* base = A + c0 * lda + i;
-  int cc = 0;
-  for (; cc + 4 <= nc; cc += 4) {
-    double v0[4], v1[4], v2[4], v3[4];
-    Row4<TA>::load(base + (int64_t)cc * lda, v0);
-    Row4<TA>::load(base + (int64_t)(cc + 1) * lda, v1);
-    Row4<TA>::load(base + (int64_t)(cc + 2) * lda, v2);
-    Row4<TA>::load(base + (int64_t)(cc + 3) * lda, v3);
-    const double t0 = ts[cc], t1 = ts[cc + 1], t2 = ts[cc + 2], t3 = ts[cc + 3];
-    const int64_t c = c0 + cc;
+  // a lower-triangular A has nothing in columns beyond the block's last row
+  int cend = nc;
+  if (TRI) {
+    const int64_t lim = i + V - c0;
+    cend = (int)(lim < 0 ? 0 : (lim < nc ? lim : nc));
+  }
+  double acc[V];
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      if (!tri || c + 3 <= i + e) {
-        a[e] += v0[e] * t0 + v1[e] * t1 + v2[e] * t2 + v3[e] * t3;
-      } else {
-        if (c <= i + e) a[e] += v0[e] * t0;
-        if (c + 1 <= i + e) a[e] += v1[e] * t1;
-        if (c + 2 <= i + e) a[e] += v2[e] * t2;
-      }
+  for (int e = 0; e < V; ++e) acc[e] = 0.0;
+  const TA* base = A + c0 * lda + i;
+  for (int cc = 0; cc < cend; cc += LN_UNROLL) {
+    uint4 a[LN_UNROLL];
+#pragma unroll
+    for (int u = 0; u < LN_UNROLL; ++u)
+      a[u] = (cc + u < cend) ? load16(base + (int64_t)(cc + u) * lda) : make_uint4(0, 0, 0, 0);
+#pragma unroll
+    for (int u = 0; u < LN_UNROLL; ++u) {
+      const double tc = ts[cc + u];   // cc + u < LN_COLS: cc < nc <= LN_COLS, a multiple of LN_UNROLL
+      const int64_t col = c0 + cc + u;
+      double v[V];
+      Vec16<TA>::expand(a[u], v);
+#pragma unroll
+      for (int e = 0; e < V; ++e) acc[e] += ((TRI && col > i + e) ? 0.0 : v[e]) * tc;
     }
   }
-  for (; cc < nc; ++cc) {
-    double v[4];
-    Row4<TA>::load(base + (int64_t)cc * lda, v);
-    const double tc = ts[cc];
+  double* out = part + (int64_t)blockIdx.y * stride + i;
 #pragma unroll
-    for (int e = 0; e < 4; ++e)
-      if (!tri || c0 + cc <= i + e) a[e] += v[e] * tc;
-  }
-  double* out = part + (int64_t)blockIdx.y * ((int64_t)gridDim.x * DN_ROWS) + i;
-#pragma unroll
-  for (int e = 0; e < 4; ++e) out[e] = a[e];
+  for (int e = 0; e < V; ++e)
+    if (i + e < nrow) out[e] = acc[e];
 }
 
 // out_i = r ? alpha (r_i - s_i) : s_i with s_i = sum_b part[b][i]
@@ -401,27 +473,39 @@ __global__ void k_finish_n(const double* __restrict__ part, int nb, int64_t stri
 }
 
 template <typename TA>
-static void gemv_t(const TA* A, int64_t nrow, int64_t lda, int64_t ncol, const double* x, double* y, int tri,
-                   double* part, hipStream_t st, int clk = -1) {
-  const int nb = cdiv(nrow, TR_ROWS);
+static int64_t lt_rows() { return 256 * Vec16<TA>::V; }
+
+// workspace (doubles) needed by gemv_t / gemv_n for an nrow x ncol operand
+template <typename TA>
+static int64_t gemv_work(int64_t nrow, int64_t ncol) {
+  const int64_t wt = cdiv(nrow, lt_rows<TA>()) * ncol;
+  const int64_t wn = cdiv(ncol, LN_COLS) * (cdiv(nrow, lt_rows<TA>()) * lt_rows<TA>());
+  return std::max(wt, wn);
+}
+
+template <typename TA, bool TRI = false>
+static void gemv_t(const TA* A, int64_t nrow, int64_t lda, int64_t ncol, const double* x, double* y, double* part,
+                   hipStream_t st, int clk = -1) {
+  const int nb = cdiv(nrow, lt_rows<TA>());
   if (clk >= 0) clk_begin(clk, st);
-  k_gemvt_part<TA><<<dim3(cdiv(ncol, TR_COLS), nb), 256, 0, st>>>(A, nrow, lda, ncol, x, part, tri);
+  k_lt_part<TA, LT_COLS, TRI><<<dim3(cdiv(ncol, LT_COLS), nb), 256, 0, st>>>(A, nrow, lda, ncol, x, part);
   LAUNCHCHK();
   if (clk >= 0) clk_end(clk, st);
   k_sum_rows<<<cdiv(ncol, 256), 256, 0, st>>>(part, nb, ncol, y);
   LAUNCHCHK();
 }
 
-template <typename TA>
+template <typename TA, bool TRI = false>
 static void gemv_n(const TA* A, int64_t nrow, int64_t lda, int64_t ncol, const double* t, const double* r,
-                   double alpha, double* out, int tri, double* part, hipStream_t st, int clk = -1) {
-  const int nb = cdiv(ncol, DN_COLS);
-  const int gx = cdiv(nrow, DN_ROWS);
+                   double alpha, double* out, double* part, hipStream_t st, int clk = -1) {
+  const int nb = cdiv(ncol, LN_COLS);
+  const int gx = cdiv(nrow, lt_rows<TA>());
+  const int64_t stride = (int64_t)gx * lt_rows<TA>();
   if (clk >= 0) clk_begin(clk, st);
-  k_gemvn_part<TA><<<dim3(gx, nb), 256, 0, st>>>(A, nrow, lda, ncol, t, part, tri);
+  k_ln_part<TA, TRI><<<dim3(gx, nb), 256, 0, st>>>(A, nrow, lda, ncol, t, part, stride);
   LAUNCHCHK();
   if (clk >= 0) clk_end(clk, st);
-  k_finish_n<<<cdiv(nrow, 256), 256, 0, st>>>(part, nb, (int64_t)gx * DN_ROWS, nrow, r, alpha, out);
+  k_finish_n<<<cdiv(nrow, 256), 256, 0, st>>>(part, nb, stride, nrow, r, alpha, out);
   LAUNCHCHK();
 }
 
@@ -431,12 +515,22 @@ static void apply_t(const ffk_precond* P, const double* r, double* z, hipStream_
   const int64_t n = P->n, k = P->k_eff;
   const double* F = P->Finv.as<double>();
   double* part = P->work.as<double>();
-  gemv_t<TA>(L, n, P->ld, k, r, P->y.as<double>(), 0, part, st, CLK_GEMV_T);
+  gemv_t<TA>(L, n, P->ld, k, r, P->y.as<double>(), part, st, CLK_GEMV_T);
   clk_begin(CLK_CORE, st);
-  gemv_n<double>(F, k, P->ldf, k, P->y.as<double>(), nullptr, 1.0, P->t1.as<double>(), 1, part, st);
-  gemv_t<double>(F, k, P->ldf, k, P->t1.as<double>(), P->t.as<double>(), 1, part, st);
+  gemv_n<double, true>(F, k, P->ldf, k, P->y.as<double>(), nullptr, 1.0, P->t1.as<double>(), part, st);
+  gemv_t<double, true>(F, k, P->ldf, k, P->t1.as<double>(), P->t.as<double>(), part, st);
   clk_end(CLK_CORE, st);
-  gemv_n<TA>(L, n, P->ld, k, P->t.as<double>(), r, 1.0 / P->lambda, z, 0, part, st, CLK_GEMV_N);
+  gemv_n<TA>(L, n, P->ld, k, P->t.as<double>(), r, 1.0 / P->lambda, z, part, st, CLK_GEMV_N);
+}
+
+int64_t precond_work_doubles(int64_t n, int64_t ld, int64_t keff, int store) {
+  (void)n;
+  const int64_t ldf = pad64(std::max<int64_t>(keff, 1));
+  int64_t w = gemv_work<double>(ldf, ldf);
+  if (store == FFK_FP64) w = std::max(w, gemv_work<double>(ld, keff));
+  else if (store == FFK_FP32) w = std::max(w, gemv_work<float>(ld, keff));
+  else w = std::max(w, gemv_work<bf16_t>(ld, keff));
+  return w;
 }
 
 __global__ void k_scale(const double* r, double a, int64_t n, double* z) {
@@ -451,7 +545,8 @@ void precond_apply(const ffk_precond* P, const double* r, double* z, hipStream_t
     return;
   }
   if (P->store == FFK_FP64) apply_t<double>(P, r, z, st);
-  else apply_t<float>(P, r, z, st);
+  else if (P->store == FFK_FP32) apply_t<float>(P, r, z, st);
+  else apply_t<bf16_t>(P, r, z, st);
 }
 
 // L (n x k_eff) as a dense column-major FP64 matrix with leading dimension n.
@@ -459,7 +554,10 @@ __global__ void k_export(const void* L, int store, int64_t n, int64_t ld, int64_
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= n * k) return;
   const int64_t c = e / n, i = e % n;
-  out[e] = store == FFK_FP64 ? static_cast<const double*>(L)[i + c * ld] : (double)static_cast<const float*>(L)[i + c * ld];
+  const int64_t a = i + c * ld;
+  out[e] = store == FFK_FP64   ? static_cast<const double*>(L)[a]
+           : store == FFK_FP32 ? (double)static_cast<const float*>(L)[a]
+                               : (double)bf2f(static_cast<const bf16_t*>(L)[a]);
 }
 
 void precond_export(const ffk_precond* P, double* L, hipStream_t st) {

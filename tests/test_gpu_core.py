@@ -201,6 +201,45 @@ def test_precond_factor_and_apply_match_oracle(ffk, ctx):
     assert float(r @ z32) > 0
 
 
+@pytest.fixture(scope="module")
+def apply_case():
+    s = system(7, 300, 330)                            # n = 6300: several row blocks and ragged tails
+    K = ok.dense_kernel(s.R, SIGMA)
+    idx = osel.select_uniform(K.shape[0], 200, 9)       # 200 columns: ragged column tiles
+    Lo, _, keff, _ = osel.incomplete_cholesky(lambda i: K[:, i], np.diag(K), len(idx), order=idx)
+    lam = 1e-3 * np.diag(K).max()
+    r = synth.random_vectors(K.shape[0], 5)
+    return s, idx, Lo[:, :keff], lam, r
+
+
+@pytest.mark.parametrize("store", ["fp64", "fp32", "bf16"])
+def test_precond_apply_storage_formats(ffk, ctx, apply_case, store):
+    s, idx, Lo, lam, r = apply_case
+    S = ffk.descriptor_build(ctx, dev(s.R), SIGMA)
+    P = ffk.precond_build(ctx, S, dev(idx, torch.int64), lam, store=ffk.PRECISIONS[store])
+    assert P.k_eff == Lo.shape[1]
+    z = host(ffk.precond_apply(ctx, P, dev(r)))
+    Ls = host(ffk.precond_export(ctx, P, S.n))
+    Lst = osv.stored_factor(Lo, store)
+    if store == "fp64":
+        np.testing.assert_allclose(Ls, Lst, rtol=0, atol=1e-10 * np.abs(Lst).max())
+        assert relerr(z, osv.woodbury(Lst, lam)(r)) <= 1e-9
+    else:
+        # the stored factor is the oracle's factor rounded to the format; an
+        # element whose FP64 value sits within rounding noise of a tie may land
+        # one unit of the format away (rare)
+        ulp = {"fp32": 2.0 ** -23, "bf16": 2.0 ** -7}[store]
+        diff = np.abs(Ls - Lst)
+        assert np.all(diff <= ulp * np.abs(Lst) + 1e-10 * np.abs(Lst).max())
+        assert np.count_nonzero(diff > 1e-10 * np.abs(Lst).max()) <= 1e-4 * Lst.size
+    # z inverts the operator built from the stored factor, to the accuracy of
+    # the FP64 Woodbury apply at this condition number
+    a, b = Ls @ (Ls.T @ z), lam * z
+    scale = (np.linalg.norm(a) + np.linalg.norm(b)) / np.linalg.norm(r)
+    assert relerr(a + b, r) <= 1e-9 * max(scale, 1.0)
+    assert float(r @ z) > 0
+
+
 def test_precond_drops_dependent_columns(ffk, ctx):
     s = system(5, 8, 305)
     S = ffk.descriptor_build(ctx, dev(s.R), SIGMA)

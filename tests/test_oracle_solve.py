@@ -95,3 +95,23 @@ def test_m9_n200_uniform_pcg_reaches_cholesky_solution():
     assert np.linalg.norm(K @ x - K @ ref) <= 2e-6 * np.linalg.norm(y)
     _, it_plain, _ = osv.pcg(A, y, None, tol=1e-6, maxiter=3 * it)
     assert it < it_plain
+
+
+def test_stored_factor_rounding():
+    one = 1.0
+    cases = {
+        1.0: 1.0,                               # representable values stay
+        -2.5: -2.5,
+        one + 2.0 ** -8: 1.0,                   # tie between 1 and 1 + 2^-7: to the even 1
+        one + 3 * 2.0 ** -8: one + 2.0 ** -6,   # tie between 1 + 2^-7 (odd) and 1 + 2^-6 (even)
+        one + 2.0 ** -8 + 2.0 ** -20: one + 2.0 ** -7,   # just above the tie
+        -(one + 2.0 ** -8 + 2.0 ** -20): -(one + 2.0 ** -7),
+    }
+    x = np.array(list(cases))
+    np.testing.assert_array_equal(osv.stored_factor(x, "bf16"), np.array(list(cases.values())))
+    rng = np.random.default_rng(3)
+    y = rng.standard_normal(10000) * 10.0 ** rng.uniform(-20, 20, 10000)
+    for fmt, eps in (("bf16", 2.0 ** -8), ("fp32", 2.0 ** -24)):
+        r = osv.stored_factor(y, fmt)
+        assert np.all(np.abs(r - y) <= eps * np.abs(y) * (1 + 1e-12))
+    np.testing.assert_array_equal(osv.stored_factor(y, "fp64"), y)
