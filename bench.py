@@ -12,7 +12,7 @@ A timed step is one pass of the whole hot path on inputs already in HBM
 (positions R and forces F): descriptor and Hessian-coefficient build,
 column selection, preconditioner build (L stored FP32, FP64 k x k core) and
 the mixed-precision PCG solve (FP64 products until the residual is below
-1e-2 |F|, then split-BF16 MFMA products with an FP64 true-residual refresh
+0.3 |F|, then split-BF16 MFMA products with an FP64 true-residual refresh
 every 10 iterations) to a true FP64 relative residual of 1e-6.  `value` is
 the mean wall time of one such solve (lower is better).  Beside it the run
 reports the plain FP64 solve of the same system (FP64 products, FP64 L), the
@@ -36,7 +36,7 @@ sys.path.insert(0, ROOT)
 PEAK_TFLOPS = {"bf16": 2500.0, "bf16x3": 2500.0, "fp32": 157.3, "fp64": 78.6}
 PEAK_HBM_GBS = 8000.0
 TOL = 1e-6
-SWITCH_BELOW = 1e-2
+SWITCH_BELOW = 0.3
 REFRESH = 10
 CLOCK_STRIDE = 16       # event pairs around every 16th launch of each clocked kernel
 
@@ -111,8 +111,9 @@ def solve(ffk, ctx, R, F, cfg, arm: str):
     t3 = time.perf_counter()
     rec = {
         "arm": arm,
-        "products": {"fp64": "fp64", "mixed": "fp64 until |r| < 1e-2 |F|, then bf16x3; fp64 refresh every 10",
-                     "mixed_fp32": "fp64 until |r| < 1e-2 |F|, then fp32; fp64 refresh every 10"}[arm],
+        "products": {"fp64": "fp64",
+                     "mixed": "fp64 until |r| < %g |F|, then bf16x3; fp64 refresh every %d" % (SWITCH_BELOW, REFRESH),
+                     "mixed_fp32": "fp64 until |r| < %g |F|, then fp32; fp64 refresh every %d" % (SWITCH_BELOW, REFRESH)}[arm],
         "L_storage": "fp32" if mixed else "fp64",
         "k_eff": int(P.k_eff), "iters": int(rep.iters), "switch_iter": int(rep.switch_iter),
         "status": int(rep.status), "rel_res_true": rep.rel_res_true, "n_refresh": int(rep.n_refresh),

@@ -32,7 +32,10 @@ def flags(debug: bool) -> list[str]:
     f = ["--offload-arch=" + ARCH, "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
          "-Wno-unused-variable", "-Wno-unused-lambda-capture",
          # no packed-FP32 instructions in the device code
-         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         # MFMA accumulators in ordinary VGPRs: otherwise the FP64 GEMM loop
+         # copies every accumulator between VGPRs and AGPRs each K step
+         "-mllvm", "-amdgpu-mfma-vgpr-form=1"]
     f += ["-O1", "-g"] if debug else ["-O3"]
     return f
 

@@ -135,7 +135,8 @@ struct ffk_ctx {
 namespace ffk {
 
 // Coefficients of the kernel for one storage precision: dA = a(r) - a(0),
-// B = b(r), as N x N row-major matrices.
+// B = b(r), as Nr x Nr row-major matrices (Nr = N rounded up to 128, zero
+// padding).
 struct CoeffSet {
   DBuf dA_hi, dA_lo;   // FP64: dA_hi holds double; FP32: float; BF16: hi (+lo for BF16X3)
   DBuf B;              // FP64: double, otherwise float
@@ -144,16 +145,16 @@ struct CoeffSet {
 
 // Per-precision MVM workspaces.
 struct MvmWork {
-  DBuf U64;            // N x D double  (J v)
+  DBuf U64, UT64;      // J v as FP64: Nr x Dk and transposed Dr x Nr (zero padding)
   DBuf pd;             // N double      (x_c,j . u_j)
   DBuf s;              // D double      (column sums of U)
   DBuf spart;          // partials of s
-  DBuf U32;            // N x D float
-  DBuf Uh, Ul;         // N x D bf16
-  DBuf UTh, UTl;       // D x N bf16
-  DBuf Wn64;           // N x N double  (-W)
-  DBuf Wn32;           // N x N float
-  DBuf Wnh, Wnl;       // N x N bf16
+  DBuf U32, UT32;      // the same in FP32
+  DBuf Uh, Ul;         // Nr x Dk bf16 hi / lo
+  DBuf UTh, UTl;       // Dr x Nr bf16 hi / lo
+  DBuf Wn64;           // Nr x Nr double  (-W, zero padding)
+  DBuf Wn32;           // Nr x Nr float
+  DBuf Wnh, Wnl;       // Nr x Nr bf16
   DBuf wpart;          // N x tilesN double (row-sum partials of W)
   DBuf G;              // N x D double
   DBuf part;           // split-K partials of GEMM 2
@@ -176,7 +177,8 @@ struct ffk_system {
   ffk::DBuf xmean;          // D double
   ffk::DBuf Xc;             // N x D double (centred)
   ffk::DBuf sqn;            // N double (|x_c|^2)
-  ffk::DBuf Xc32;           // N x D float
+  ffk::DBuf Xp64, XpT64;    // X_c as FP64, padded: Nr x Dk and transposed Dr x Nr
+  ffk::DBuf Xp32, XpT32;    // the same in FP32
   ffk::DBuf Xch, Xcl;       // N x D bf16 hi/lo
   ffk::DBuf XcTh, XcTl;     // D x N bf16 hi/lo
   ffk::CoeffSet coef[4];    // indexed by ffk_precision

@@ -68,6 +68,7 @@ struct EpiCoeff {
   double* dA;
   double* B;
   int N;
+  int64_t ld;                  // leading dimension of dA and B (padded)
   double inv_len, a0, bcoef;   // sqrt(5)/sigma, 5/(3 sigma^2), 25/(3 sigma^4)
   template <typename T, int TM, int TN, class Acc>
   __device__ void run(const Acc (&acc)[TM][TN], const FragCoord& f, char*) const {
@@ -83,8 +84,8 @@ struct EpiCoeff {
             r2 = (r == c || r2 < 0.0) ? 0.0 : r2;
             const double z = sqrt(r2) * inv_len;
             const double em = expm1(-z);
-            dA[(int64_t)r * N + c] = a0 * ((1.0 + z) * em + z);
-            B[(int64_t)r * N + c] = -bcoef * (em + 1.0);
+            dA[(int64_t)r * ld + c] = a0 * ((1.0 + z) * em + z);
+            B[(int64_t)r * ld + c] = -bcoef * (em + 1.0);
           }
         }
   }
@@ -126,10 +127,6 @@ void descriptor_build(ffk_system* s, const double* R, hipStream_t st) {
 }
 
 // ------------------------------------------------------------ conversions ----
-__global__ void k_to_f32(const double* __restrict__ a, float* __restrict__ b, int64_t n) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e < n) b[e] = (float)a[e];
-}
 
 // hi/lo split of a rows x cols FP64 matrix into padded bf16 arrays
 // (rows_p x ld_out); entries outside rows x cols are written as zero.
@@ -181,6 +178,37 @@ __global__ void k_split_transpose(const double* __restrict__ a, int64_t rows, in
 
 static int64_t rup(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
 
+// out[c][r] = (T)a[r][c] for the rows x cols FP64 matrix a (lda), into a
+// cols_p x ld_out array, zero outside.  64 x 64 tiles through LDS.
+template <typename T>
+__global__ void k_pad_transpose(const double* __restrict__ a, int64_t rows, int64_t cols, int64_t lda,
+                                int64_t cols_p, int64_t ld_out, T* __restrict__ out) {
+  __shared__ double tile[64][65];
+  const int64_t r0 = (int64_t)blockIdx.x * 64, c0 = (int64_t)blockIdx.y * 64;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  for (int i = ty; i < 64; i += 4) {
+    const int64_t r = r0 + i, c = c0 + tx;
+    tile[i][tx] = (r < rows && c < cols) ? a[r * lda + c] : 0.0;
+  }
+  __syncthreads();
+  for (int i = ty; i < 64; i += 4) {
+    const int64_t c = c0 + i, r = r0 + tx;
+    if (c < cols_p && r < ld_out) out[c * ld_out + r] = (T)tile[tx][i];
+  }
+}
+
+// (T)a into a rows_p x ld_out array (row-major), zero outside rows x cols.
+template <typename T>
+__global__ void k_pad_copy(const double* __restrict__ a, int64_t rows, int64_t cols, int64_t lda, int64_t rows_p,
+                           int64_t ld_out, T* __restrict__ out) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= rows_p * ld_out) return;
+  const int64_t r = e / ld_out, c = e % ld_out;
+  out[e] = (r < rows && c < cols) ? (T)a[r * lda + c] : T(0);
+}
+
+
+
 void k_split_transpose_launch(const double* a, int64_t rows, int64_t cols, int64_t lda, int64_t cols_p,
                               int64_t ld_out, bf16_t* hi, bf16_t* lo, hipStream_t st) {
   dim3 grid(cdiv(ld_out, 64), cdiv(cols_p, 64));
@@ -188,13 +216,23 @@ void k_split_transpose_launch(const double* a, int64_t rows, int64_t cols, int64
   LAUNCHCHK();
 }
 
+template <typename T>
+static void padded_descriptor(const ffk_system* s, DBuf& P, DBuf& PT, hipStream_t st) {
+  const int64_t N = s->N, D = s->D;
+  const int64_t Nr = rup(N, 128), Dk = rup(D, 64), Dr = rup(D, 128);
+  P.alloc(Nr * Dk * sizeof(T));
+  k_pad_copy<T><<<cdiv(Nr * Dk, 256), 256, 0, st>>>(s->Xc.as<double>(), N, D, D, Nr, Dk, P.as<T>());
+  LAUNCHCHK();
+  PT.alloc(Dr * Nr * sizeof(T));
+  dim3 grid(cdiv(Nr, 64), cdiv(Dr, 64));
+  k_pad_transpose<T><<<grid, 256, 0, st>>>(s->Xc.as<double>(), N, D, D, Dr, Nr, PT.as<T>());
+  LAUNCHCHK();
+}
+
 void ensure_lowp_descriptor(ffk_system* s, int prec, hipStream_t st) {
   const int64_t N = s->N, D = s->D;
-  if (prec == FFK_FP32 && !s->Xc32) {
-    s->Xc32.alloc(N * D * sizeof(float));
-    k_to_f32<<<cdiv(N * D, 256), 256, 0, st>>>(s->Xc.as<double>(), s->Xc32.as<float>(), N * D);
-    LAUNCHCHK();
-  }
+  if (prec == FFK_FP64 && !s->Xp64) padded_descriptor<double>(s, s->Xp64, s->XpT64, st);
+  if (prec == FFK_FP32 && !s->Xp32) padded_descriptor<float>(s, s->Xp32, s->XpT32, st);
   if ((prec == FFK_BF16 || prec == FFK_BF16X3) && !s->Xch) {
     const int64_t Nr = rup(N, 128), Dk = rup(D, 64), Dr = rup(D, 128);
     s->Xch.alloc(Nr * Dk * 2);
@@ -213,16 +251,19 @@ void ensure_lowp_descriptor(ffk_system* s, int prec, hipStream_t st) {
 
 void ensure_coeffs(ffk_system* s, int prec, hipStream_t st) {
   const int64_t N = s->N;
+  const int64_t Nr = rup(N, 128);
   CoeffSet& c64 = s->coef[FFK_FP64];
   if (!c64.ready) {
-    c64.dA_hi.alloc(N * N * sizeof(double));
-    c64.B.alloc(N * N * sizeof(double));
+    c64.dA_hi.alloc(Nr * Nr * sizeof(double));
+    c64.B.alloc(Nr * Nr * sizeof(double));
+    HIPCHK(hipMemsetAsync(c64.dA_hi.get(), 0, Nr * Nr * sizeof(double), st));
+    HIPCHK(hipMemsetAsync(c64.B.get(), 0, Nr * Nr * sizeof(double), st));
     ScalarArgs<double> g{};
     g.M = (int)N;
     g.N = (int)N;
     g.nseg = 1;
     g.seg[0] = SegS<double>{s->Xc.as<double>(), s->D, 1, s->Xc.as<double>(), s->D, 1, (int)s->D};
-    EpiCoeff e{s->sqn.as<double>(), c64.dA_hi.as<double>(), c64.B.as<double>(), (int)N,
+    EpiCoeff e{s->sqn.as<double>(), c64.dA_hi.as<double>(), c64.B.as<double>(), (int)N, Nr,
                sqrt(5.0) / s->sigma, s->a0, s->bcoef};
     dim3 grid(cdiv(N, 128), cdiv(N, 128));
     gemm_scalar_kernel<double, 128, 128, 16, true, true, EpiCoeff><<<grid, 256, 0, st>>>(g, e);
@@ -233,23 +274,23 @@ void ensure_coeffs(ffk_system* s, int prec, hipStream_t st) {
   CoeffSet& cs = s->coef[prec];
   if (cs.ready) return;
   if (prec == FFK_FP32) {
-    cs.dA_hi.alloc(N * N * sizeof(float));
-    cs.B.alloc(N * N * sizeof(float));
-    k_to_f32<<<cdiv(N * N, 256), 256, 0, st>>>(c64.dA_hi.as<double>(), cs.dA_hi.as<float>(), N * N);
+    cs.dA_hi.alloc(Nr * Nr * sizeof(float));
+    cs.B.alloc(Nr * Nr * sizeof(float));
+    k_pad_copy<float><<<cdiv(Nr * Nr, 256), 256, 0, st>>>(c64.dA_hi.as<double>(), N, N, Nr, Nr, Nr,
+                                                          cs.dA_hi.as<float>());
     LAUNCHCHK();
-    k_to_f32<<<cdiv(N * N, 256), 256, 0, st>>>(c64.B.as<double>(), cs.B.as<float>(), N * N);
+    k_pad_copy<float><<<cdiv(Nr * Nr, 256), 256, 0, st>>>(c64.B.as<double>(), N, N, Nr, Nr, Nr, cs.B.as<float>());
     LAUNCHCHK();
   } else {
-    const int64_t Nr = rup(N, 128);
     const bool x3 = (prec == FFK_BF16X3);
     cs.dA_hi.alloc(Nr * Nr * 2);
     if (x3) cs.dA_lo.alloc(Nr * Nr * 2);
     cs.B.alloc(Nr * Nr * sizeof(float));
-    k_split_pad<<<cdiv(Nr * Nr, 256), 256, 0, st>>>(c64.dA_hi.as<double>(), N, N, N, Nr, Nr,
+    k_split_pad<<<cdiv(Nr * Nr, 256), 256, 0, st>>>(c64.dA_hi.as<double>(), N, N, Nr, Nr, Nr,
                                                     cs.dA_hi.as<bf16_t>(),
                                                     x3 ? cs.dA_lo.as<bf16_t>() : nullptr);
     LAUNCHCHK();
-    k_f32_pad<<<cdiv(Nr * Nr, 256), 256, 0, st>>>(c64.B.as<double>(), N, N, N, Nr, Nr, cs.B.as<float>());
+    k_f32_pad<<<cdiv(Nr * Nr, 256), 256, 0, st>>>(c64.B.as<double>(), N, N, Nr, Nr, Nr, cs.B.as<float>());
     LAUNCHCHK();
   }
   cs.ready = true;

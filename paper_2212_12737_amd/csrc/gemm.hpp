@@ -328,7 +328,7 @@ template <int N> struct VmCnt {
   static constexpr unsigned v = (unsigned)((N & 0xF) | ((N >> 4) << 14) | (0x7 << 4) | (0xF << 8));
 };
 
-__device__ inline void dma16(const bf16_t* g, bf16_t* lds_base) {
+__device__ inline void dma16(const void* g, void* lds_base) {
   __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1)))*)g,
                                    (void __attribute__((address_space(3)))*)lds_base, 16, 0, 0);
 }
@@ -351,11 +351,60 @@ __device__ inline void tile_coords(int& tm, int& tn) {
   tn = in / gsz;
 }
 
-template <int BM, int BN, int S, bool X3, class Epi>
-__global__ __launch_bounds__(256) void gemm_bf16_dma_kernel(Bf16Args g, Epi epi) {
-  constexpr int BK = 32;
+// Per element type: what one pair of 16-byte operand fragments (one 64-byte
+// K chunk of a 16-row group per lane group) feeds to the matrix cores.
+//   bf16:   8 elements, one v_mfma_f32_16x16x32_bf16
+//   float:  4 elements, four v_mfma_f32_16x16x4_f32 (instruction j takes
+//           element j of every lane: K slot l/16 of instruction j is k = 4(l/16)+j)
+//   double: 2 elements, two v_mfma_f64_16x16x4_f64 (k = 2(l/16)+j)
+// Every K index is consumed exactly once by A and B alike, so the sum is the
+// full dot product whatever the order.
+template <typename T> struct DmaMfma;
+template <> struct DmaMfma<bf16_t> {
+  typedef f4 acc_t;
+  typedef float scalar_t;
+  static constexpr int SLICES = 1;
+  __device__ static inline acc_t slice(const u4& a, const u4& b, acc_t c, int) { return mfma_bf16(a, b, c); }
+};
+template <> struct DmaMfma<float> {
+  typedef f4 acc_t;
+  typedef float scalar_t;
+  static constexpr int SLICES = 4;
+  __device__ static inline acc_t slice(const u4& a, const u4& b, acc_t c, int j) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a[j]), __uint_as_float(b[j]), c, 0, 0, 0);
+  }
+};
+template <> struct DmaMfma<double> {
+  typedef d4 acc_t;
+  typedef double scalar_t;
+  static constexpr int SLICES = 2;
+  __device__ static inline acc_t slice(const u4& a, const u4& b, acc_t c, int j) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(__hiloint2double((int)a[2 * j + 1], (int)a[2 * j]),
+                                                 __hiloint2double((int)b[2 * j + 1], (int)b[2 * j]), c, 0, 0, 0);
+  }
+};
+
+// Operand segment of the pipelined engine: K-contiguous arrays of T whose row
+// count is padded to the tile and whose leading dimension (in elements) and K
+// are multiples of 64 bytes; padding is zero.  The lo arrays are used only in
+// the split-BF16 mode.
+struct SegD {
+  const void *Ah, *Al;
+  const void *Bh, *Bl;
+  int64_t lda, ldb;   // elements
+  int K;              // elements, multiple of 64 bytes
+};
+struct DmaArgs {
+  int nseg;
+  SegD seg[2];
+};
+
+template <typename T, int BM, int BN, int S, bool X3, class Epi>
+__global__ __launch_bounds__(256) void gemm_dma_kernel(DmaArgs g, Epi epi) {
+  static_assert(!X3 || sizeof(T) == 2, "the split mode is for bf16 operands");
+  constexpr int BK = 64 / (int)sizeof(T);               // one 64-byte chunk of each row per K tile
   constexpr int NARR = X3 ? 2 : 1;
-  constexpr int GROUP_BYTES = 1024;                     // 16 rows x 32 k x 2 B
+  constexpr int GROUP_BYTES = 1024;                     // 16 rows x 64 bytes
   constexpr int GA = BM / 16, GB = BN / 16;             // row groups per operand tile
   constexpr int A_BYTES = GA * GROUP_BYTES;
   constexpr int B_BYTES = GB * GROUP_BYTES;
@@ -363,6 +412,7 @@ __global__ __launch_bounds__(256) void gemm_bf16_dma_kernel(Bf16Args g, Epi epi)
   constexpr int QA = GA / 4, QB = GB / 4;               // groups loaded per wave
   constexpr int LPT = NARR * (QA + QB);                 // wave-wide loads per tile per wave
   constexpr int TM = BM / 32, TN = BN / 32;             // 16x16 blocks per wave (2 x 2 waves)
+  typedef typename DmaMfma<T>::acc_t acc_t;
   __shared__ __attribute__((aligned(1024))) char smem[S * STAGE_BYTES];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -375,33 +425,32 @@ __global__ __launch_bounds__(256) void gemm_bf16_dma_kernel(Bf16Args g, Epi epi)
   const int tb = (int)((int64_t)T_ * blockIdx.z / gridDim.z);
   const int te = (int)((int64_t)T_ * (blockIdx.z + 1) / gridDim.z);
 
-  f4 acc[TM][TN];
+  acc_t acc[TM][TN];
 #pragma unroll
   for (int i = 0; i < TM; ++i)
 #pragma unroll
-    for (int j = 0; j < TN; ++j) acc[i][j] = f4{0, 0, 0, 0};
+    for (int j = 0; j < TN; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
 
   // lane L of a group load: row L%16, 16-byte chunk L/16
   const int lrow = lane & 15, lchunk = lane >> 4;
   auto issue = [&](int t) {
-    const SegB& sg = (t < t0) ? g.seg[0] : g.seg[1];
-    const int k0 = (t < t0 ? t : t - t0) * BK + lchunk * 8;
+    const SegD& sg = (t < t0) ? g.seg[0] : g.seg[1];
+    const int64_t k0 = (int64_t)(t < t0 ? t : t - t0) * BK + lchunk * (16 / (int)sizeof(T));
     char* st = smem + (t % S) * STAGE_BYTES;
 #pragma unroll
     for (int h = 0; h < NARR; ++h) {
-      const bf16_t* A = h ? sg.Al : sg.Ah;
-      const bf16_t* B = h ? sg.Bl : sg.Bh;
+      const T* A = static_cast<const T*>(h ? sg.Al : sg.Ah);
+      const T* B = static_cast<const T*>(h ? sg.Bl : sg.Bh);
 #pragma unroll
       for (int q = 0; q < QA; ++q) {
         const int grp = wave * QA + q;
-        dma16(A + (int64_t)(m0 + grp * 16 + lrow) * sg.lda + k0,
-              reinterpret_cast<bf16_t*>(st + h * A_BYTES + grp * GROUP_BYTES));
+        dma16(A + (int64_t)(m0 + grp * 16 + lrow) * sg.lda + k0, st + h * A_BYTES + grp * GROUP_BYTES);
       }
 #pragma unroll
       for (int q = 0; q < QB; ++q) {
         const int grp = wave * QB + q;
         dma16(B + (int64_t)(n0 + grp * 16 + lrow) * sg.ldb + k0,
-              reinterpret_cast<bf16_t*>(st + NARR * A_BYTES + h * B_BYTES + grp * GROUP_BYTES));
+              st + NARR * A_BYTES + h * B_BYTES + grp * GROUP_BYTES);
       }
     }
   };
@@ -429,20 +478,43 @@ __global__ __launch_bounds__(256) void gemm_bf16_dma_kernel(Bf16Args g, Epi epi)
       bh[j] = *reinterpret_cast<const u4*>(st + NARR * A_BYTES + (wn * TN + j) * GROUP_BYTES + lane * 16);
       if (X3) bl[X3 ? j : 0] = *reinterpret_cast<const u4*>(st + NARR * A_BYTES + B_BYTES + (wn * TN + j) * GROUP_BYTES + lane * 16);
     }
+    // FP64: slice-outer order, so consecutive instructions update different
+    // accumulators (measured faster); FP32 and BF16: block-outer order
+    if (sizeof(T) != 8) {
 #pragma unroll
-    for (int i = 0; i < TM; ++i)
+      for (int i = 0; i < TM; ++i)
 #pragma unroll
-      for (int j = 0; j < TN; ++j) {
-        if (X3) {
-          acc[i][j] = mfma_bf16(al[X3 ? i : 0], bh[j], acc[i][j]);
-          acc[i][j] = mfma_bf16(ah[i], bl[X3 ? j : 0], acc[i][j]);
-        }
-        acc[i][j] = mfma_bf16(ah[i], bh[j], acc[i][j]);
+        for (int j = 0; j < TN; ++j)
+#pragma unroll
+          for (int sl = 0; sl < DmaMfma<T>::SLICES; ++sl) {
+            if (X3) {
+              acc[i][j] = DmaMfma<T>::slice(al[X3 ? i : 0], bh[j], acc[i][j], sl);
+              acc[i][j] = DmaMfma<T>::slice(ah[i], bl[X3 ? j : 0], acc[i][j], sl);
+            }
+            acc[i][j] = DmaMfma<T>::slice(ah[i], bh[j], acc[i][j], sl);
+          }
+    } else
+#pragma unroll
+    for (int sl = 0; sl < DmaMfma<T>::SLICES; ++sl) {
+      if (X3) {
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+          for (int j = 0; j < TN; ++j) acc[i][j] = DmaMfma<T>::slice(al[X3 ? i : 0], bh[j], acc[i][j], sl);
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+          for (int j = 0; j < TN; ++j) acc[i][j] = DmaMfma<T>::slice(ah[i], bl[X3 ? j : 0], acc[i][j], sl);
       }
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) acc[i][j] = DmaMfma<T>::slice(ah[i], bh[j], acc[i][j], sl);
+    }
   }
   __syncthreads();
-  FragCoord fc{m0 + wm * (BM / 2), n0 + wn * (BN / 2), lane, m0, n0, false, tni};
-  epi.template run<float, TM, TN>(acc, fc, smem);
+  FragCoord fc{m0 + wm * (BM / 2), n0 + wn * (BN / 2), lane, m0, n0, sizeof(T) == 8, tni};
+  epi.template run<typename DmaMfma<T>::scalar_t, TM, TN>(acc, fc, smem);
 }
 
 // Shared LDS for epilogues that need it: the engines pass their operand LDS

@@ -22,13 +22,15 @@ static int64_t rup(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
 // U the chosen precision needs (FP64, FP32, or split BF16 in both layouts).
 constexpr int GT = 16;
 
-template <bool W64, bool W32, bool WBF>
+// MODE: 0 = FP64, 1 = FP32, 2 = split BF16 (hi in U/UT, lo in Ul/UTl).
+// U is written row-major with leading dimension ldu; UT (if not null) is the
+// transposed copy with leading dimension ldut.  Padding is left untouched.
+template <int MODE>
 __global__ __launch_bounds__(256) void k_jv_tile(const double* __restrict__ R, const int* __restrict__ pairs,
                                                  const double* __restrict__ v, const double* __restrict__ Xc,
-                                                 int64_t N, int M, int64_t D, double* __restrict__ U64,
-                                                 float* __restrict__ U32, bf16_t* __restrict__ Uh,
-                                                 bf16_t* __restrict__ Ul, int64_t ldu, bf16_t* __restrict__ UTh,
-                                                 bf16_t* __restrict__ UTl, int64_t ldut, double* __restrict__ pd,
+                                                 int64_t N, int M, int64_t D, void* __restrict__ U,
+                                                 void* __restrict__ Ul, int64_t ldu, void* __restrict__ UT,
+                                                 void* __restrict__ UTl, int64_t ldut, double* __restrict__ pd,
                                                  double* __restrict__ cpart) {
   extern __shared__ double sm[];
   const int m3 = 3 * M;
@@ -49,7 +51,7 @@ __global__ __launch_bounds__(256) void k_jv_tile(const double* __restrict__ R, c
     const int pq = pairs[d];
     const int p = 3 * (pq >> 16), q = 3 * (pq & 0xFFFF);
     double cs = 0.0;
-    float uf[GT];
+    double ug[GT];
 #pragma unroll
     for (int gl = 0; gl < GT; ++gl) {
       double u = 0.0;
@@ -59,33 +61,34 @@ __global__ __launch_bounds__(256) void k_jv_tile(const double* __restrict__ R, c
         const double dx = Rg[p] - Rg[q], dy = Rg[p + 1] - Rg[q + 1], dz = Rg[p + 2] - Rg[q + 2];
         const double ir = 1.0 / sqrt(dx * dx + dy * dy + dz * dz);
         u = -(dx * (vg[p] - vg[q]) + dy * (vg[p + 1] - vg[q + 1]) + dz * (vg[p + 2] - vg[q + 2])) * (ir * ir * ir);
-        const int64_t o = (g0 + gl) * D + d;
-        pdp[gl] += u * Xc[o];
-        if (W64) U64[o] = u;
-        if (W32) U32[o] = (float)u;
-        if (WBF) {
+        pdp[gl] += u * Xc[(g0 + gl) * D + d];
+        const int64_t o = (g0 + gl) * ldu + d;
+        if (MODE == 0) static_cast<double*>(U)[o] = u;
+        if (MODE == 1) static_cast<float*>(U)[o] = (float)u;
+        if (MODE == 2) {
           const float f = (float)u;
           const bf16_t h = f2bf(f);
-          Uh[(g0 + gl) * ldu + d] = h;
-          Ul[(g0 + gl) * ldu + d] = f2bf(f - bf2f(h));
+          static_cast<bf16_t*>(U)[o] = h;
+          static_cast<bf16_t*>(Ul)[o] = f2bf(f - bf2f(h));
         }
       }
       cs += u;
-      uf[gl] = (float)u;
+      ug[gl] = u;
     }
     cpart[(int64_t)blockIdx.x * D + d] = cs;
-    if (WBF) {   // transposed copy: 16 consecutive geometries of row d
-      bf16_t hh[GT], ll[GT];
-#pragma unroll
-      for (int gl = 0; gl < GT; ++gl) {
-        hh[gl] = f2bf(uf[gl]);
-        ll[gl] = f2bf(uf[gl] - bf2f(hh[gl]));
-      }
+    if (UT) {   // transposed copy: ng consecutive geometries of row d
 #pragma unroll
       for (int gl = 0; gl < GT; ++gl)
         if (gl < ng) {
-          UTh[d * ldut + g0 + gl] = hh[gl];
-          UTl[d * ldut + g0 + gl] = ll[gl];
+          const int64_t o = d * ldut + g0 + gl;
+          if (MODE == 0) static_cast<double*>(UT)[o] = ug[gl];
+          if (MODE == 1) static_cast<float*>(UT)[o] = (float)ug[gl];
+          if (MODE == 2) {
+            const float f = (float)ug[gl];
+            const bf16_t h = f2bf(f);
+            static_cast<bf16_t*>(UT)[o] = h;
+            static_cast<bf16_t*>(UTl)[o] = f2bf(f - bf2f(h));
+          }
         }
     }
   }
@@ -393,46 +396,48 @@ static void mvm_gemms_scalar(const MvmArgs& a, const T* Xt, const T* Xs, const T
   }
 }
 
-template <bool X3>
-static void mvm_gemms_bf16(ffk_system* s, int prec, const MvmArgs& a, hipStream_t st, hipEvent_t* ev) {
-  const int64_t N = s->N, D = s->D;
-  const int64_t Nr = rup(N, 128), Dk = rup(D, 64), Dr = rup(D, 128);
-  MvmWork& w = s->work;
-  CoeffSet& cs = s->coef[prec];
+// Both GEMMs of the product on the pipelined MFMA engine, for element type T
+// (double, float or bf16; X3 = split BF16).  Operands are the padded arrays:
+// X_c (Nr x Dk) and its transpose (Dr x Nr), U likewise, dA, B and -W (Nr x Nr).
+template <typename T, bool X3, typename CT, class EpiW1>
+static void mvm_gemms_dma(const MvmArgs& a, int64_t Nr, int64_t Dk, int64_t Dr, const void* Xh, const void* Xl,
+                          const void* XTh, const void* XTl, const void* Uh, const void* Ul, const void* UTh,
+                          const void* UTl, const void* dAh, const void* dAl, const void* Wh, const void* Wl,
+                          const EpiW1& epw, hipStream_t st, hipEvent_t* ev) {
+  const int64_t N = a.Nt, D = a.D;
   const int ntn = (int)(Nr / 128);
   {
-    Bf16Args g{};
+    DmaArgs g{};
     g.nseg = 1;
-    g.seg[0] = SegB{s->Xch.as<bf16_t>(), s->Xcl.as<bf16_t>(), w.Uh.as<bf16_t>(), w.Ul.as<bf16_t>(), Dk, Dk, (int)Dk};
-    EpiWbf<128, X3> e{cs.B.as<float>(), Nr, a.pd, w.Wnh.as<bf16_t>(), w.Wnl.as<bf16_t>(), a.wpart, ntn, (int)N};
+    g.seg[0] = SegD{Xh, Xl, Uh, Ul, Dk, Dk, (int)Dk};
     clk_begin(CLK_GEMM1, st);
-    gemm_bf16_dma_kernel<128, 128, 4, X3, EpiWbf<128, X3>><<<dim3(ntn, ntn), 256, 0, st>>>(g, e);
+    gemm_dma_kernel<T, 128, 128, 4, X3, EpiW1><<<dim3(ntn, ntn), 256, 0, st>>>(g, epw);
     LAUNCHCHK();
     clk_end(CLK_GEMM1, st);
   }
   mark(ev, 3, st);
-  Bf16Args g{};
+  DmaArgs g{};
   g.nseg = 2;
-  g.seg[0] = SegB{cs.dA_hi.as<bf16_t>(), cs.dA_lo.as<bf16_t>(), w.UTh.as<bf16_t>(), w.UTl.as<bf16_t>(), Nr, Nr, (int)Nr};
-  g.seg[1] = SegB{w.Wnh.as<bf16_t>(), w.Wnl.as<bf16_t>(), s->XcTh.as<bf16_t>(), s->XcTl.as<bf16_t>(), Nr, Nr, (int)Nr};
+  g.seg[0] = SegD{dAh, dAl, UTh, UTl, Nr, Nr, (int)Nr};
+  g.seg[1] = SegD{Wh, Wl, XTh, XTl, Nr, Nr, (int)Nr};
   const int64_t tiles = (Dr / 128) * ntn;
-  int splits = pick_splits(tiles, 2 * Nr / 32);
-  while (splits > 1 && (size_t)splits * N * D * sizeof(float) > a.part_bytes) splits >>= 1;
+  int splits = pick_splits(tiles, 2 * Nr / (64 / (int64_t)sizeof(T)));
+  while (splits > 1 && (size_t)splits * N * D * sizeof(CT) > a.part_bytes) splits >>= 1;
   if (splits == 1) {
     EpiG<128> e{a.s, a.Xt64, D, a.wpart, ntn, a.a0, a.G, D, (int)N, (int)D};
     clk_begin(CLK_GEMM2, st);
-    gemm_bf16_dma_kernel<128, 128, 4, X3, EpiG<128>><<<dim3(Dr / 128, ntn), 256, 0, st>>>(g, e);
+    gemm_dma_kernel<T, 128, 128, 4, X3, EpiG<128>><<<dim3(Dr / 128, ntn), 256, 0, st>>>(g, e);
     LAUNCHCHK();
     clk_end(CLK_GEMM2, st);
   } else {
-    EpiPart<float> e{static_cast<float*>(a.part), D, (int)N, (int)D};
+    EpiPart<CT> e{static_cast<CT*>(a.part), D, (int)N, (int)D};
     clk_begin(CLK_GEMM2, st);
-    gemm_bf16_dma_kernel<128, 128, 4, X3, EpiPart<float>><<<dim3(Dr / 128, ntn, splits), 256, 0, st>>>(g, e);
+    gemm_dma_kernel<T, 128, 128, 4, X3, EpiPart<CT>><<<dim3(Dr / 128, ntn, splits), 256, 0, st>>>(g, e);
     LAUNCHCHK();
     clk_end(CLK_GEMM2, st);
     clk_begin(CLK_GEMM2_REDUCE, st);
-    k_g_reduce<float><<<N, 256, 0, st>>>(static_cast<const float*>(a.part), splits, N, D, a.s, a.Xt64, a.wpart, ntn,
-                                         a.a0, a.G);
+    k_g_reduce<CT><<<N, 256, 0, st>>>(static_cast<const CT*>(a.part), splits, N, D, a.s, a.Xt64, a.wpart, ntn,
+                                      a.a0, a.G);
     LAUNCHCHK();
     clk_end(CLK_GEMM2_REDUCE, st);
   }
@@ -451,26 +456,28 @@ static void ensure_work(ffk_system* s, int prec, hipStream_t st) {
     w.wpart.alloc(N * (rup(N, 128) / 128) * 8);
     w.part.alloc(part_budget(N, D));
   }
+  const int64_t Nr = rup(N, 128), Dk = rup(D, 64), Dr = rup(D, 128);
+  // padding rows/columns stay zero: the kernels write only the valid part
+  auto zeroed = [&](DBuf& b, int64_t bytes) {
+    b.alloc(bytes);
+    HIPCHK(hipMemsetAsync(b.get(), 0, bytes, st));
+  };
   if (prec == FFK_FP64 && !w.U64) {
-    w.U64.alloc(N * D * 8);
-    w.Wn64.alloc(N * N * 8);
+    zeroed(w.U64, Nr * Dk * 8);
+    zeroed(w.UT64, Dr * Nr * 8);
+    zeroed(w.Wn64, Nr * Nr * 8);
   }
   if (prec == FFK_FP32 && !w.U32) {
-    w.U32.alloc(N * D * 4);
-    w.Wn32.alloc(N * N * 4);
+    zeroed(w.U32, Nr * Dk * 4);
+    zeroed(w.UT32, Dr * Nr * 4);
+    zeroed(w.Wn32, Nr * Nr * 4);
   }
   if ((prec == FFK_BF16 || prec == FFK_BF16X3) && !w.Uh) {
-    const int64_t Nr = rup(N, 128), Dk = rup(D, 64), Dr = rup(D, 128);
-    w.Uh.alloc(Nr * Dk * 2);
-    w.Ul.alloc(Nr * Dk * 2);
-    w.UTh.alloc(Dr * Nr * 2);
-    w.UTl.alloc(Dr * Nr * 2);
-    // padding rows/columns stay zero: the front kernel writes only the valid part
-    HIPCHK(hipMemsetAsync(w.Uh.get(), 0, Nr * Dk * 2, st));
-    HIPCHK(hipMemsetAsync(w.Ul.get(), 0, Nr * Dk * 2, st));
-    HIPCHK(hipMemsetAsync(w.UTh.get(), 0, Dr * Nr * 2, st));
-    HIPCHK(hipMemsetAsync(w.UTl.get(), 0, Dr * Nr * 2, st));
-    w.Wnh.alloc(Nr * Nr * 2);
+    zeroed(w.Uh, Nr * Dk * 2);
+    zeroed(w.Ul, Nr * Dk * 2);
+    zeroed(w.UTh, Dr * Nr * 2);
+    zeroed(w.UTl, Dr * Nr * 2);
+    w.Wnh.alloc(Nr * Nr * 2);   // every entry is written by the GEMM 1 epilogue
     w.Wnl.alloc(Nr * Nr * 2);
   }
 }
@@ -485,7 +492,6 @@ void kernel_mvm_ev(ffk_system* s, const double* v, double* y, double shift, int 
   const int64_t N = s->N, D = s->D;
   const int M = s->M;
   MvmWork& w = s->work;
-  const bool bf = (prec == FFK_BF16 || prec == FFK_BF16X3);
   const int64_t Nr = rup(N, 128), ldu = rup(D, 64);
   const int nblk = cdiv(N, GT);
   const size_t shm = (size_t)2 * GT * 3 * M * sizeof(double);
@@ -493,18 +499,14 @@ void kernel_mvm_ev(ffk_system* s, const double* v, double* y, double shift, int 
   double* cp = w.spart.as<double>();
   clk_begin(CLK_JV, st);
   if (prec == FFK_FP64)
-    k_jv_tile<true, false, false><<<nblk, 256, shm, st>>>(s->R.as<double>(), s->pairs.as<int>(), v, s->Xc.as<double>(),
-                                                          N, M, D, w.U64.as<double>(), nullptr, nullptr, nullptr, 0,
-                                                          nullptr, nullptr, 0, pd, cp);
+    k_jv_tile<0><<<nblk, 256, shm, st>>>(s->R.as<double>(), s->pairs.as<int>(), v, s->Xc.as<double>(), N, M, D,
+                                         w.U64.get(), nullptr, ldu, w.UT64.get(), nullptr, Nr, pd, cp);
   else if (prec == FFK_FP32)
-    k_jv_tile<false, true, false><<<nblk, 256, shm, st>>>(s->R.as<double>(), s->pairs.as<int>(), v, s->Xc.as<double>(),
-                                                          N, M, D, nullptr, w.U32.as<float>(), nullptr, nullptr, 0,
-                                                          nullptr, nullptr, 0, pd, cp);
+    k_jv_tile<1><<<nblk, 256, shm, st>>>(s->R.as<double>(), s->pairs.as<int>(), v, s->Xc.as<double>(), N, M, D,
+                                         w.U32.get(), nullptr, ldu, w.UT32.get(), nullptr, Nr, pd, cp);
   else
-    k_jv_tile<false, false, true><<<nblk, 256, shm, st>>>(s->R.as<double>(), s->pairs.as<int>(), v, s->Xc.as<double>(),
-                                                          N, M, D, nullptr, nullptr, w.Uh.as<bf16_t>(),
-                                                          w.Ul.as<bf16_t>(), ldu, w.UTh.as<bf16_t>(),
-                                                          w.UTl.as<bf16_t>(), Nr, pd, cp);
+    k_jv_tile<2><<<nblk, 256, shm, st>>>(s->R.as<double>(), s->pairs.as<int>(), v, s->Xc.as<double>(), N, M, D,
+                                         w.Uh.get(), w.Ul.get(), ldu, w.UTh.get(), w.UTl.get(), Nr, pd, cp);
   LAUNCHCHK();
   clk_end(CLK_JV, st);
   mark(ev, 1, st);
@@ -516,18 +518,29 @@ void kernel_mvm_ev(ffk_system* s, const double* v, double* y, double shift, int 
   MvmArgs a{N, N, D, s->a0, s->Xc.as<double>(), pd, w.s.as<double>(), w.wpart.as<double>(), w.G.as<double>(),
             w.part.get(), w.part.bytes()};
   CoeffSet& cs = s->coef[prec];
+  const int ntn = (int)(Nr / 128);
+  const int64_t Dk = rup(D, 64), Dr = rup(D, 128);
   if (prec == FFK_FP64) {
-    mvm_gemms_scalar<double>(a, s->Xc.as<double>(), s->Xc.as<double>(), w.U64.as<double>(), cs.dA_hi.as<double>(),
-                             cs.B.as<double>(), w.Wn64.as<double>(), st, ev);
+    EpiW<double, 128> e{cs.B.as<double>(), Nr, pd, w.Wn64.as<double>(), Nr, a.wpart, ntn, (int)N, (int)N};
+    mvm_gemms_dma<double, false, double>(a, Nr, Dk, Dr, s->Xp64.get(), nullptr, s->XpT64.get(), nullptr,
+                                         w.U64.get(), nullptr, w.UT64.get(), nullptr, cs.dA_hi.get(), nullptr,
+                                         w.Wn64.get(), nullptr, e, st, ev);
   } else if (prec == FFK_FP32) {
-    mvm_gemms_scalar<float>(a, s->Xc32.as<float>(), s->Xc32.as<float>(), w.U32.as<float>(), cs.dA_hi.as<float>(),
-                            cs.B.as<float>(), w.Wn32.as<float>(), st, ev);
+    EpiW<float, 128> e{cs.B.as<float>(), Nr, pd, w.Wn32.as<float>(), Nr, a.wpart, ntn, (int)N, (int)N};
+    mvm_gemms_dma<float, false, float>(a, Nr, Dk, Dr, s->Xp32.get(), nullptr, s->XpT32.get(), nullptr, w.U32.get(),
+                                       nullptr, w.UT32.get(), nullptr, cs.dA_hi.get(), nullptr, w.Wn32.get(),
+                                       nullptr, e, st, ev);
   } else if (prec == FFK_BF16X3) {
-    mvm_gemms_bf16<true>(s, prec, a, st, ev);
+    EpiWbf<128, true> e{cs.B.as<float>(), Nr, pd, w.Wnh.as<bf16_t>(), w.Wnl.as<bf16_t>(), a.wpart, ntn, (int)N};
+    mvm_gemms_dma<bf16_t, true, float>(a, Nr, Dk, Dr, s->Xch.get(), s->Xcl.get(), s->XcTh.get(), s->XcTl.get(),
+                                       w.Uh.get(), w.Ul.get(), w.UTh.get(), w.UTl.get(), cs.dA_hi.get(),
+                                       cs.dA_lo.get(), w.Wnh.get(), w.Wnl.get(), e, st, ev);
   } else {
-    mvm_gemms_bf16<false>(s, prec, a, st, ev);
+    EpiWbf<128, false> e{cs.B.as<float>(), Nr, pd, w.Wnh.as<bf16_t>(), nullptr, a.wpart, ntn, (int)N};
+    mvm_gemms_dma<bf16_t, false, float>(a, Nr, Dk, Dr, s->Xch.get(), nullptr, s->XcTh.get(), nullptr, w.Uh.get(),
+                                        nullptr, w.UTh.get(), nullptr, cs.dA_hi.get(), nullptr, w.Wnh.get(),
+                                        nullptr, e, st, ev);
   }
-  (void)bf;
   mark(ev, 4, st);
   const int tb = M <= 64 ? 64 : 128;
   clk_begin(CLK_JTG, st);
@@ -591,9 +604,9 @@ void kernel_predict(const ffk_system* tr, const ffk_system* te, const double* al
   DBuf Xt(Nt * D * 8), sqt(Nt * 8), dA(Nt * Ns * 8), B(Nt * Ns * 8), Wn(Nt * Ns * 8);
   const int ntn = cdiv(Ns, 128);
   DBuf wpart(Nt * ntn * 8), G(Nt * D * 8), part(part_budget(Nt, D));
-  k_jv_tile<true, false, false><<<nblk, 256, (size_t)2 * GT * 3 * M * sizeof(double), st>>>(
-      tr->R.as<double>(), tr->pairs.as<int>(), alpha, tr->Xc.as<double>(), Ns, M, D, U.as<double>(), nullptr, nullptr,
-      nullptr, 0, nullptr, nullptr, 0, pd.as<double>(), cpart.as<double>());
+  k_jv_tile<0><<<nblk, 256, (size_t)2 * GT * 3 * M * sizeof(double), st>>>(
+      tr->R.as<double>(), tr->pairs.as<int>(), alpha, tr->Xc.as<double>(), Ns, M, D, U.get(), nullptr, D, nullptr,
+      nullptr, 0, pd.as<double>(), cpart.as<double>());
   LAUNCHCHK();
   clk_begin(CLK_COLSUM, st);
   k_colsum_final<<<cdiv(D, 64), 256, 0, st>>>(cpart.as<double>(), nblk, D, sv.as<double>());

@@ -322,9 +322,12 @@ template <typename TA> __device__ inline uint4 load16(const TA* p) {
 }
 
 constexpr int LT_COLS = 16;    // columns per block of the transposed product
-constexpr int LN_COLS = 256;   // columns per block of the direct product
 constexpr int LN_UNROLL = 16;  // loads in flight per lane in the direct product
-static_assert(LN_COLS % LN_UNROLL == 0 && LN_COLS <= 256, "direct-product column tile");
+// columns per block of the direct product: wide for the tall L (few partial
+// sums to combine), narrow for the k x k triangle (enough blocks to fill the GPU)
+template <bool TRI> constexpr int ln_cols() { return TRI ? 32 : 256; }
+static_assert(ln_cols<false>() % LN_UNROLL == 0 && ln_cols<false>() <= 256, "direct-product column tile");
+static_assert(ln_cols<true>() % LN_UNROLL == 0, "direct-product column tile");
 
 // Sum of v[0..C) over the 64 lanes of a wave, one column per lane group:
 // recursive halving (each exchange step hands half of the values to the
@@ -412,16 +415,17 @@ __global__ void k_sum_rows(const double* __restrict__ part, int nb, int64_t ncol
 }
 
 // part[blockIdx.y][i] = sum over the block's columns c of A[i + c lda] t[c]
-// (only c <= i when TRI).  Block: 256 lanes x V rows, LN_COLS columns.
+// (only c <= i when TRI).  Block: 256 lanes x V rows, ln_cols<TRI>() columns.
 template <typename TA, bool TRI>
 __global__ __launch_bounds__(256) void k_ln_part(const TA* __restrict__ A, int64_t nrow, int64_t lda, int64_t ncol,
                                                  const double* __restrict__ t, double* __restrict__ part,
                                                  int64_t stride) {
   constexpr int V = Vec16<TA>::V;
-  __shared__ double ts[LN_COLS];
-  const int64_t c0 = (int64_t)blockIdx.y * LN_COLS;
-  const int nc = (int)(ncol - c0 < LN_COLS ? ncol - c0 : LN_COLS);
-  for (int c = threadIdx.x; c < LN_COLS; c += 256) ts[c] = c < nc ? t[c0 + c] : 0.0;
+  constexpr int CB = ln_cols<TRI>();
+  __shared__ double ts[CB];
+  const int64_t c0 = (int64_t)blockIdx.y * CB;
+  const int nc = (int)(ncol - c0 < CB ? ncol - c0 : CB);
+  for (int c = threadIdx.x; c < CB; c += 256) ts[c] = c < nc ? t[c0 + c] : 0.0;
   __syncthreads();
   const int64_t i = (int64_t)blockIdx.x * (256 * V) + (int64_t)threadIdx.x * V;
   if (i >= nrow) return;
@@ -442,7 +446,7 @@ __global__ __launch_bounds__(256) void k_ln_part(const TA* __restrict__ A, int64
       a[u] = (cc + u < cend) ? load16(base + (int64_t)(cc + u) * lda) : make_uint4(0, 0, 0, 0);
 #pragma unroll
     for (int u = 0; u < LN_UNROLL; ++u) {
-      const double tc = ts[cc + u];   // cc + u < LN_COLS: cc < nc <= LN_COLS, a multiple of LN_UNROLL
+      const double tc = ts[cc + u];   // cc + u < CB: cc < nc <= CB, a multiple of LN_UNROLL
       const int64_t col = c0 + cc + u;
       double v[V];
       Vec16<TA>::expand(a[u], v);
@@ -476,10 +480,10 @@ template <typename TA>
 static int64_t lt_rows() { return 256 * Vec16<TA>::V; }
 
 // workspace (doubles) needed by gemv_t / gemv_n for an nrow x ncol operand
-template <typename TA>
+template <typename TA, bool TRI>
 static int64_t gemv_work(int64_t nrow, int64_t ncol) {
   const int64_t wt = cdiv(nrow, lt_rows<TA>()) * ncol;
-  const int64_t wn = cdiv(ncol, LN_COLS) * (cdiv(nrow, lt_rows<TA>()) * lt_rows<TA>());
+  const int64_t wn = cdiv(ncol, ln_cols<TRI>()) * (cdiv(nrow, lt_rows<TA>()) * lt_rows<TA>());
   return std::max(wt, wn);
 }
 
@@ -498,7 +502,7 @@ static void gemv_t(const TA* A, int64_t nrow, int64_t lda, int64_t ncol, const d
 template <typename TA, bool TRI = false>
 static void gemv_n(const TA* A, int64_t nrow, int64_t lda, int64_t ncol, const double* t, const double* r,
                    double alpha, double* out, double* part, hipStream_t st, int clk = -1) {
-  const int nb = cdiv(ncol, LN_COLS);
+  const int nb = cdiv(ncol, ln_cols<TRI>());
   const int gx = cdiv(nrow, lt_rows<TA>());
   const int64_t stride = (int64_t)gx * lt_rows<TA>();
   if (clk >= 0) clk_begin(clk, st);
@@ -526,10 +530,10 @@ static void apply_t(const ffk_precond* P, const double* r, double* z, hipStream_
 int64_t precond_work_doubles(int64_t n, int64_t ld, int64_t keff, int store) {
   (void)n;
   const int64_t ldf = pad64(std::max<int64_t>(keff, 1));
-  int64_t w = gemv_work<double>(ldf, ldf);
-  if (store == FFK_FP64) w = std::max(w, gemv_work<double>(ld, keff));
-  else if (store == FFK_FP32) w = std::max(w, gemv_work<float>(ld, keff));
-  else w = std::max(w, gemv_work<bf16_t>(ld, keff));
+  int64_t w = gemv_work<double, true>(ldf, ldf);
+  if (store == FFK_FP64) w = std::max(w, gemv_work<double, false>(ld, keff));
+  else if (store == FFK_FP32) w = std::max(w, gemv_work<float, false>(ld, keff));
+  else w = std::max(w, gemv_work<bf16_t, false>(ld, keff));
   return w;
 }
 
