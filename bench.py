@@ -5,21 +5,28 @@
 
 Workload (default): M = 21 atoms, N = 2000 geometries (n = 126000 unknowns,
 D = 210 inverse distances), Matern-5/2 sigma = 10, lambda = 1e-9, Nystroem
-rank k = 2000 from pivoted-Cholesky selection; seeded synthetic geometries and
-Morse + Coulomb-like forces.
+rank k = 2000; seeded synthetic geometries and Morse + Coulomb-like forces.
 
-A timed step is one pass of the whole hot path on inputs already in HBM
-(positions R and forces F): descriptor and Hessian-coefficient build,
-column selection, preconditioner build (L stored FP32, FP64 k x k core) and
-the mixed-precision PCG solve (FP64 products until the residual is below
-0.3 |F|, then split-BF16 MFMA products with an FP64 true-residual refresh
-every 10 iterations) to a true FP64 relative residual of 1e-6.  `value` is
-the mean wall time of one such solve (lower is better).  Beside it the run
-reports the plain FP64 solve of the same system (FP64 products, FP64 L), the
-kernel-product rates per precision (here and at the M = 60, N = 20000
-system), the per-kernel HIP-event clocks of the timed steps with the roofline
-entry of the kernel that took the most time, and the FP64 CPU oracle timed on
-a bounded sample of the same solve.
+Before the timed region the score network is trained for this molecule:
+exact ridge-leverage labels (dense FP64 Cholesky on the GPU) of a few small
+systems of the same molecule with other displacement seeds, then Adam on the
+GPU.  Its cost is reported as `learned_setup`; like the paper's
+molecule-specific reuse it is paid once per molecule, not per solve.
+
+A timed step is one pass of the hot path on inputs already in HBM (positions
+R and forces F): descriptor and Hessian-coefficient build, learned column
+selection (BF16 network inference, then weighted sampling), preconditioner
+build (L stored FP32, FP64 k x k core) and the mixed-precision PCG solve
+(FP64 products until the residual is below 0.3 |F|, then split-BF16 MFMA
+products with an FP64 true-residual refresh every 10 iterations) to a true
+FP64 relative residual of 1e-6.  `value` is the mean wall time of one such
+solve (lower is better).  Beside it the run reports the plain FP64 solve of
+the same system with the workload's own selection (pivoted Cholesky, FP64
+products, FP64 L), the mixed solve with that selection, the kernel-product
+rates per precision (here and at the M = 60, N = 20000 system), the
+per-kernel HIP-event clocks of the timed steps with the roofline entry of the
+kernel that took the most time, and the FP64 CPU oracle timed on a bounded
+sample of the same solve.
 """
 from __future__ import annotations
 
@@ -91,36 +98,77 @@ def mvm_rates(ffk, ctx, cfg, S, v, steps, warmup):
     return out
 
 
-def solve(ffk, ctx, R, F, cfg, arm: str):
-    """One pass of the hot path from R and F in HBM; returns (alpha, record)."""
+def solve(ffk, ctx, R, F, cfg, arm: str, net=None):
+    """One pass of the hot path from R and F in HBM; returns (alpha, record).
+
+    arm: "mixed" (learned selection when `net` is given), "mixed_pivchol",
+    "mixed_fp32" (FP32 products instead of split BF16) or "fp64" (the plain
+    FP64 solve with the workload's own selection)."""
     import torch
+    from paper_2212_12737_amd import learned
     mixed = arm != "fp64"
+    strategy = "learned" if (arm in ("mixed", "mixed_fp32") and net is not None) else cfg.strategy
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     S = ffk.descriptor_build(ctx, R, cfg.sigma)
-    idx = ffk.nystrom_select(ctx, S, cfg.strategy, cfg.k, lam=cfg.lam, seed=cfg.sel_seed)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    P = ffk.precond_build(ctx, S, idx, cfg.lam, store=ffk.FP32 if mixed else ffk.FP64)
-    torch.cuda.synchronize()
-    t2 = time.perf_counter()
-    prec = {"fp64": ffk.FP64, "mixed": ffk.BF16X3, "mixed_fp32": ffk.FP32}[arm]
+    t_desc = time.perf_counter() - t0
+    store = ffk.FP32 if mixed else ffk.FP64
+    if strategy == "learned":
+        P, how = learned.build_with_fallback(ctx, net, S, cfg.k, cfg.lam, cfg.sel_seed, store=store)
+        torch.cuda.synchronize()
+        t1 = t2 = time.perf_counter()   # selection and build are one call here
+    else:
+        how = strategy
+        idx = ffk.nystrom_select(ctx, S, strategy, cfg.k, lam=cfg.lam, seed=cfg.sel_seed)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        P = ffk.precond_build(ctx, S, idx, cfg.lam, store=store)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+    prec = {"fp64": ffk.FP64, "mixed": ffk.BF16X3, "mixed_pivchol": ffk.BF16X3, "mixed_fp32": ffk.FP32}[arm]
     alpha, rep = ffk.pcg_solve(ctx, S, P, F, cfg.lam, tol=TOL, max_iter=50000, prec=prec, refresh_every=REFRESH,
                                escalate=True, switch_below=SWITCH_BELOW if mixed else 0.0)
     torch.cuda.synchronize()
     t3 = time.perf_counter()
+    sched = "fp64 until |r| < %g |F|, then %s; fp64 refresh every %d"
     rec = {
-        "arm": arm,
-        "products": {"fp64": "fp64",
-                     "mixed": "fp64 until |r| < %g |F|, then bf16x3; fp64 refresh every %d" % (SWITCH_BELOW, REFRESH),
-                     "mixed_fp32": "fp64 until |r| < %g |F|, then fp32; fp64 refresh every %d" % (SWITCH_BELOW, REFRESH)}[arm],
+        "arm": arm, "selection": how,
+        "products": {"fp64": "fp64", "mixed": sched % (SWITCH_BELOW, "bf16x3", REFRESH),
+                     "mixed_pivchol": sched % (SWITCH_BELOW, "bf16x3", REFRESH),
+                     "mixed_fp32": sched % (SWITCH_BELOW, "fp32", REFRESH)}[arm],
         "L_storage": "fp32" if mixed else "fp64",
         "k_eff": int(P.k_eff), "iters": int(rep.iters), "switch_iter": int(rep.switch_iter),
         "status": int(rep.status), "rel_res_true": rep.rel_res_true, "n_refresh": int(rep.n_refresh),
         "n_escalations": int(rep.n_escalations), "final_prec": int(rep.final_prec),
-        "t_descriptor_select_s": t1 - t0, "t_build_s": t2 - t1, "t_pcg_s": t3 - t2, "t_total_s": t3 - t0,
+        "t_descriptor_s": t_desc, "t_select_s": (t1 - t0 - t_desc) if strategy != "learned" else None,
+        "t_build_s": (t2 - t1) if strategy != "learned" else None,
+        "t_select_build_s": t2 - t0 - t_desc, "t_pcg_s": t3 - t2, "t_total_s": t3 - t0,
     }
     return alpha, rec
+
+
+def train_network(ffk, ctx, cfg, systems: int, N: int, steps: int):
+    """Score network for this molecule from exact labels of small systems
+    (same molecule, displacement seeds disjoint from the workload's)."""
+    import torch
+    import synth
+    from paper_2212_12737_amd import learned
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    S_tr, y_tr = [], []
+    for t in range(systems):
+        st = synth.config_system(cfg, N=N, disp_seed=cfg.disp_seed + 1000 + t)
+        S = ffk.descriptor_build(ctx, torch.as_tensor(st.R, device="cuda"), cfg.sigma)
+        S_tr.append(S)
+        y_tr.append(learned.make_labels(ctx, S, cfg.lam))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    net, tl = learned.train(ctx, S_tr, y_tr, H=256, steps=steps, batch=256, lr=1e-3, seed=7, log_every=steps // 4)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    return net, {"systems": systems, "N_each": N, "steps": steps, "t_labels_s": t1 - t0, "t_train_s": t2 - t1,
+                 "loss_first": tl.losses[0][1], "loss_last": tl.losses[-1][1],
+                 "label": "exact ridge leverage, dense FP64 Cholesky on the GPU"}
 
 
 def source_digest(paths):
@@ -206,6 +254,10 @@ def main(argv=None) -> int:
     ap.add_argument("--mvm-steps", type=int, default=20)
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison solve")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle sample")
+    ap.add_argument("--train-systems", type=int, default=4, help="small systems labelled for the score network")
+    ap.add_argument("--train-n", type=int, default=500, help="geometries per training system")
+    ap.add_argument("--train-steps", type=int, default=2000)
+    ap.add_argument("--no-learned", action="store_true", help="time the workload's own selection instead")
     ap.add_argument("--kernels-only", type=int, default=0,
                     help="counter-collection mode: build once, run this many preconditioner applies and products, "
                          "plus a plain copy of known size for calibration; prints no JSON line")
@@ -245,15 +297,19 @@ def main(argv=None) -> int:
         log("kernels-only done: %d applies and products, k_eff %d" % (a.kernels_only, P.k_eff))
         return 0
 
+    net, setup = None, None
+    if not a.no_learned:
+        net, setup = train_network(ffk, ctx, cfg, a.train_systems, a.train_n, a.train_steps)
+        log("score network:", json.dumps(setup))
     for _ in range(a.warmup):
-        _, rec = solve(ffk, ctx, R, F, cfg, "mixed")
+        _, rec = solve(ffk, ctx, R, F, cfg, "mixed", net)
         log("warmup solve", json.dumps(rec))
     ffk.clock_enable(ctx, CLOCK_STRIDE)
     recs = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(a.steps):
-        alpha, rec = solve(ffk, ctx, R, F, cfg, "mixed")
+        alpha, rec = solve(ffk, ctx, R, F, cfg, "mixed", net)
         recs.append(rec)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -290,7 +346,10 @@ def main(argv=None) -> int:
     if not a.no_fp64:
         _, arms["fp64"] = solve(ffk, ctx, R, F, cfg, "fp64")
         log("fp64 solve", json.dumps(arms["fp64"]))
-        _, arms["mixed_fp32"] = solve(ffk, ctx, R, F, cfg, "mixed_fp32")
+        if net is not None:
+            _, arms["mixed_pivchol"] = solve(ffk, ctx, R, F, cfg, "mixed_pivchol")
+            log("mixed solve, workload's selection", json.dumps(arms["mixed_pivchol"]))
+        _, arms["mixed_fp32"] = solve(ffk, ctx, R, F, cfg, "mixed_fp32", net)
         log("mixed fp32 solve", json.dumps(arms["mixed_fp32"]))
 
     S = ffk.descriptor_build(ctx, R, cfg.sigma)
@@ -318,11 +377,14 @@ def main(argv=None) -> int:
         "n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "ms_per_step": sec * 1e3,
         "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
         "dtype": "bf16x3+fp64", "data": "synthetic",
-        "config": {"workload": "%s: M=%d atoms, N=%d geometries, n=%d unknowns, D=%d, lambda=%g, k=%d %s Nystroem, "
-                               "full solve (descriptor, selection, preconditioner build, mixed PCG to 1e-6)"
-                               % (cfg.name, cfg.M, cfg.N, n, cfg.D, cfg.lam, cfg.k, cfg.strategy),
+        "config": {"workload": "%s: M=%d atoms, N=%d geometries, n=%d unknowns, D=%d, lambda=%g, k=%d Nystroem, "
+                               "full solve (descriptor, %s selection, preconditioner build, mixed PCG to 1e-6)"
+                               % (cfg.name, cfg.M, cfg.N, n, cfg.D, cfg.lam, cfg.k,
+                                  "learned" if net is not None else cfg.strategy),
                    "M": cfg.M, "N": cfg.N, "n": n, "D": cfg.D, "lambda": cfg.lam, "k": cfg.k,
-                   "strategy": cfg.strategy, "parallelism": "single GPU"},
+                   "strategy": "learned" if net is not None else cfg.strategy,
+                   "fp64_arm_strategy": cfg.strategy, "parallelism": "single GPU"},
+        "learned_setup": setup,
         "converged": ok_all,
         "roofline": roof,
         "kernel_clocks_ms": clock_ms,

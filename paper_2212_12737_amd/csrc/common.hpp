@@ -287,6 +287,11 @@ void mlp_prepare_inputs(const ffk_mlp* net, const ffk_system* s, float* out, int
 void mlp_fit_norm(ffk_mlp* net, const float* X, int64_t B, hipStream_t st);
 void block_log_scores(const double* tau, int64_t N, int M, float* y, hipStream_t st);
 
+// Row padding of the product's N- and D-sized operands: a multiple of every
+// GEMM tile edge, so tiles never read past an array.
+constexpr int64_t kRowPad = 256;
+inline int64_t pad_rows(int64_t n) { return (n + kRowPad - 1) / kRowPad * kRowPad; }
+
 // clock.cpp -- per-kernel event clocks (ids match ffk_clock in ffkrr.h)
 enum ClockId {
   CLK_JV = 0, CLK_COLSUM, CLK_GEMM1, CLK_GEMM2, CLK_GEMM2_REDUCE, CLK_JTG,

@@ -219,7 +219,7 @@ void k_split_transpose_launch(const double* a, int64_t rows, int64_t cols, int64
 template <typename T>
 static void padded_descriptor(const ffk_system* s, DBuf& P, DBuf& PT, hipStream_t st) {
   const int64_t N = s->N, D = s->D;
-  const int64_t Nr = rup(N, 128), Dk = rup(D, 64), Dr = rup(D, 128);
+  const int64_t Nr = pad_rows(N), Dk = rup(D, 64), Dr = pad_rows(D);
   P.alloc(Nr * Dk * sizeof(T));
   k_pad_copy<T><<<cdiv(Nr * Dk, 256), 256, 0, st>>>(s->Xc.as<double>(), N, D, D, Nr, Dk, P.as<T>());
   LAUNCHCHK();
@@ -234,7 +234,7 @@ void ensure_lowp_descriptor(ffk_system* s, int prec, hipStream_t st) {
   if (prec == FFK_FP64 && !s->Xp64) padded_descriptor<double>(s, s->Xp64, s->XpT64, st);
   if (prec == FFK_FP32 && !s->Xp32) padded_descriptor<float>(s, s->Xp32, s->XpT32, st);
   if ((prec == FFK_BF16 || prec == FFK_BF16X3) && !s->Xch) {
-    const int64_t Nr = rup(N, 128), Dk = rup(D, 64), Dr = rup(D, 128);
+    const int64_t Nr = pad_rows(N), Dk = rup(D, 64), Dr = pad_rows(D);
     s->Xch.alloc(Nr * Dk * 2);
     s->Xcl.alloc(Nr * Dk * 2);
     k_split_pad<<<cdiv(Nr * Dk, 256), 256, 0, st>>>(s->Xc.as<double>(), N, D, D, Nr, Dk,
@@ -251,7 +251,7 @@ void ensure_lowp_descriptor(ffk_system* s, int prec, hipStream_t st) {
 
 void ensure_coeffs(ffk_system* s, int prec, hipStream_t st) {
   const int64_t N = s->N;
-  const int64_t Nr = rup(N, 128);
+  const int64_t Nr = pad_rows(N);
   CoeffSet& c64 = s->coef[FFK_FP64];
   if (!c64.ready) {
     c64.dA_hi.alloc(Nr * Nr * sizeof(double));

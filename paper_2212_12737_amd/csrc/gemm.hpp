@@ -59,6 +59,7 @@ struct FragCoord {
   int m0, n0;           // absolute origin of the block tile
   bool f64;             // FP64 MFMA output layout
   int tn;               // tile column index (n0 / BN)
+  int wcol, nwcol;      // this wave's column index among the block's wave columns
   __device__ inline int row(int tm, int v) const {
     return wm0 + tm * 16 + (f64 ? 4 * v + (lane >> 4) : 4 * (lane >> 4) + v);
   }
@@ -186,7 +187,7 @@ __global__ __launch_bounds__(256) void gemm_scalar_kernel(ScalarArgs<TI> g, Epi 
     if (t + 1 < te) store(buf ^ 1);
     __syncthreads();
   }
-  FragCoord fc{m0 + wm0, n0 + wn0, lane, m0, n0, sizeof(T) == 8, (int)blockIdx.x};
+  FragCoord fc{m0 + wm0, n0 + wn0, lane, m0, n0, sizeof(T) == 8, (int)blockIdx.x, wave & 1, 2};
   epi.template run<T, TM, TN>(acc, fc, reinterpret_cast<char*>(&As[0][0][0]));
 }
 
@@ -309,7 +310,7 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(Bf16Args g, Epi epi) {
       __syncthreads();
     }
   }
-  FragCoord fc{m0 + wm0, n0 + wn0, lane, m0, n0, false, (int)blockIdx.x};
+  FragCoord fc{m0 + wm0, n0 + wn0, lane, m0, n0, false, (int)blockIdx.x, wave & 1, 2};
   epi.template run<float, TM, TN>(acc, fc, reinterpret_cast<char*>(&As[0][0]));
 }
 
@@ -399,19 +400,30 @@ struct DmaArgs {
   SegD seg[2];
 };
 
-template <typename T, int BM, int BN, int S, bool X3, class Epi>
-__global__ __launch_bounds__(256) void gemm_dma_kernel(DmaArgs g, Epi epi) {
+// Tile shape of the pipelined engine: BM x BN block tile computed by WM x WN
+// waves (each (BM/WM) x (BN/WN)), S pipeline stages.
+template <int BM_, int BN_, int WM_, int WN_, int S_>
+struct DmaTile {
+  static constexpr int BM = BM_, BN = BN_, WM = WM_, WN = WN_, S = S_;
+  static constexpr int NT = 64 * WM * WN;
+};
+
+template <typename T, class TL, bool X3, class Epi>
+__global__ __launch_bounds__(TL::NT) void gemm_dma_kernel(DmaArgs g, Epi epi) {
   static_assert(!X3 || sizeof(T) == 2, "the split mode is for bf16 operands");
+  constexpr int BM = TL::BM, BN = TL::BN, WM = TL::WM, WN = TL::WN, S = TL::S, NW = WM * WN;
   constexpr int BK = 64 / (int)sizeof(T);               // one 64-byte chunk of each row per K tile
   constexpr int NARR = X3 ? 2 : 1;
   constexpr int GROUP_BYTES = 1024;                     // 16 rows x 64 bytes
   constexpr int GA = BM / 16, GB = BN / 16;             // row groups per operand tile
+  static_assert(GA % NW == 0 && GB % NW == 0, "row groups must split evenly over the waves");
   constexpr int A_BYTES = GA * GROUP_BYTES;
   constexpr int B_BYTES = GB * GROUP_BYTES;
   constexpr int STAGE_BYTES = NARR * (A_BYTES + B_BYTES);
-  constexpr int QA = GA / 4, QB = GB / 4;               // groups loaded per wave
+  constexpr int QA = GA / NW, QB = GB / NW;             // groups loaded per wave
   constexpr int LPT = NARR * (QA + QB);                 // wave-wide loads per tile per wave
-  constexpr int TM = BM / 32, TN = BN / 32;             // 16x16 blocks per wave (2 x 2 waves)
+  static_assert(LPT * (S > 2 ? S - 2 : 0) < 64, "vmcnt holds at most 63 loads in flight");
+  constexpr int TM = BM / WM / 16, TN = BN / WN / 16;   // 16x16 blocks per wave
   typedef typename DmaMfma<T>::acc_t acc_t;
   __shared__ __attribute__((aligned(1024))) char smem[S * STAGE_BYTES];
 
@@ -419,7 +431,7 @@ __global__ __launch_bounds__(256) void gemm_dma_kernel(DmaArgs g, Epi epi) {
   int tmi, tni;
   tile_coords(tmi, tni);
   const int m0 = tmi * BM, n0 = tni * BN;
-  const int wm = wave >> 1, wn = wave & 1;
+  const int wm = wave / WN, wn = wave % WN;
   const int t0 = g.seg[0].K / BK;
   const int T_ = t0 + (g.nseg > 1 ? g.seg[1].K / BK : 0);
   const int tb = (int)((int64_t)T_ * blockIdx.z / gridDim.z);
@@ -513,7 +525,7 @@ __global__ __launch_bounds__(256) void gemm_dma_kernel(DmaArgs g, Epi epi) {
     }
   }
   __syncthreads();
-  FragCoord fc{m0 + wm * (BM / 2), n0 + wn * (BN / 2), lane, m0, n0, sizeof(T) == 8, tni};
+  FragCoord fc{m0 + wm * (BM / WM), n0 + wn * (BN / WN), lane, m0, n0, sizeof(T) == 8, tni, wn, WN};
   epi.template run<typename DmaMfma<T>::scalar_t, TM, TN>(acc, fc, smem);
 }
 

@@ -175,8 +175,7 @@ struct EpiW {
   int Nr, Nc;   // valid rows / cols
   template <typename T, int TM, int TN, class Acc>
   __device__ void run(const Acc (&acc)[TM][TN], const FragCoord& f, char* smem) const {
-    double* red = reinterpret_cast<double*>(smem);   // [2][BM]
-    const int wn = (f.wn0 - f.n0) != 0;
+    double* red = reinterpret_cast<double*>(smem);   // [wave columns][BM]
 #pragma unroll
     for (int i = 0; i < TM; ++i)
 #pragma unroll
@@ -196,12 +195,16 @@ struct EpiW {
         rs += __shfl_xor(rs, 2);
         rs += __shfl_xor(rs, 4);
         rs += __shfl_xor(rs, 8);
-        if ((f.lane & 15) == 0) red[wn * BM + (r - f.m0)] = rs;
+        if ((f.lane & 15) == 0) red[f.wcol * BM + (r - f.m0)] = rs;
       }
     __syncthreads();
     for (int t = threadIdx.x; t < BM; t += blockDim.x) {
       const int r = f.m0 + t;
-      if (r < Nr) wpart[(int64_t)r * ntn + f.tn] = red[t] + red[BM + t];
+      if (r < Nr) {
+        double a = 0.0;
+        for (int q = 0; q < f.nwcol; ++q) a += red[q * BM + t];
+        wpart[(int64_t)r * ntn + f.tn] = a;
+      }
     }
   }
 };
@@ -217,8 +220,7 @@ struct EpiWbf {
   int N;
   template <typename T, int TM, int TN, class Acc>
   __device__ void run(const Acc (&acc)[TM][TN], const FragCoord& f, char* smem) const {
-    double* red = reinterpret_cast<double*>(smem);
-    const int wn = (f.wn0 - f.n0) != 0;
+    double* red = reinterpret_cast<double*>(smem);   // [wave columns][BM]
 #pragma unroll
     for (int i = 0; i < TM; ++i)
 #pragma unroll
@@ -239,12 +241,16 @@ struct EpiWbf {
         rs += __shfl_xor(rs, 2);
         rs += __shfl_xor(rs, 4);
         rs += __shfl_xor(rs, 8);
-        if ((f.lane & 15) == 0) red[wn * BM + (r - f.m0)] = rs;
+        if ((f.lane & 15) == 0) red[f.wcol * BM + (r - f.m0)] = rs;
       }
     __syncthreads();
     for (int t = threadIdx.x; t < BM; t += blockDim.x) {
       const int r = f.m0 + t;
-      if (r < N) wpart[(int64_t)r * ntn + f.tn] = red[t] + red[BM + t];
+      if (r < N) {
+        double a = 0.0;
+        for (int q = 0; q < f.nwcol; ++q) a += red[q * BM + t];
+        wpart[(int64_t)r * ntn + f.tn] = a;
+      }
     }
   }
 };
@@ -397,42 +403,59 @@ static void mvm_gemms_scalar(const MvmArgs& a, const T* Xt, const T* Xs, const T
 }
 
 // Both GEMMs of the product on the pipelined MFMA engine, for element type T
-// (double, float or bf16; X3 = split BF16).  Operands are the padded arrays:
-// X_c (Nr x Dk) and its transpose (Dr x Nr), U likewise, dA, B and -W (Nr x Nr).
-template <typename T, bool X3, typename CT, class EpiW1>
-static void mvm_gemms_dma(const MvmArgs& a, int64_t Nr, int64_t Dk, int64_t Dr, const void* Xh, const void* Xl,
-                          const void* XTh, const void* XTl, const void* Uh, const void* Ul, const void* UTh,
-                          const void* UTl, const void* dAh, const void* dAl, const void* Wh, const void* Wl,
-                          const EpiW1& epw, hipStream_t st, hipEvent_t* ev) {
+// (double, float or bf16; X3 = split BF16) and tile shapes TL1 (GEMM 1) and
+// TL2 (GEMM 2).  Operands are the padded arrays: X_c (Nr x Dk) and its
+// transpose (Dr x Nr), U likewise, dA, B and -W (Nr x Nr).
+struct DmaOps {
+  const void *Xh, *Xl, *XTh, *XTl;   // X_c
+  const void *Uh, *Ul, *UTh, *UTl;   // U = J v
+  const void *dAh, *dAl;             // dA
+  const void* Bc;                    // B (FP64 for FP64, FP32 otherwise)
+  void *Wh, *Wl;                     // -W
+};
+
+template <typename T, bool X3, typename CT, class TL1, class TL2>
+static void mvm_gemms_dma(const MvmArgs& a, int64_t Nr, int64_t Dk, int64_t Dr, const DmaOps& o, hipStream_t st,
+                          hipEvent_t* ev) {
   const int64_t N = a.Nt, D = a.D;
-  const int ntn = (int)(Nr / 128);
+  const int ntn = (int)(Nr / TL1::BN);   // GEMM 1 tile columns = row-sum partials per row
   {
     DmaArgs g{};
     g.nseg = 1;
-    g.seg[0] = SegD{Xh, Xl, Uh, Ul, Dk, Dk, (int)Dk};
+    g.seg[0] = SegD{o.Xh, o.Xl, o.Uh, o.Ul, Dk, Dk, (int)Dk};
+    const dim3 grid((unsigned)(Nr / TL1::BN), (unsigned)(Nr / TL1::BM));
     clk_begin(CLK_GEMM1, st);
-    gemm_dma_kernel<T, 128, 128, 4, X3, EpiW1><<<dim3(ntn, ntn), 256, 0, st>>>(g, epw);
+    if constexpr (sizeof(T) == 2) {
+      EpiWbf<TL1::BM, X3> e{static_cast<const float*>(o.Bc), Nr, a.pd, static_cast<bf16_t*>(o.Wh),
+                            static_cast<bf16_t*>(o.Wl), a.wpart, ntn, (int)N};
+      gemm_dma_kernel<T, TL1, X3, decltype(e)><<<grid, TL1::NT, 0, st>>>(g, e);
+    } else {
+      EpiW<T, TL1::BM> e{static_cast<const T*>(o.Bc), Nr, a.pd, static_cast<T*>(o.Wh), Nr, a.wpart, ntn, (int)N,
+                         (int)N};
+      gemm_dma_kernel<T, TL1, X3, decltype(e)><<<grid, TL1::NT, 0, st>>>(g, e);
+    }
     LAUNCHCHK();
     clk_end(CLK_GEMM1, st);
   }
   mark(ev, 3, st);
   DmaArgs g{};
   g.nseg = 2;
-  g.seg[0] = SegD{dAh, dAl, UTh, UTl, Nr, Nr, (int)Nr};
-  g.seg[1] = SegD{Wh, Wl, XTh, XTl, Nr, Nr, (int)Nr};
-  const int64_t tiles = (Dr / 128) * ntn;
+  g.seg[0] = SegD{o.dAh, o.dAl, o.UTh, o.UTl, Nr, Nr, (int)Nr};
+  g.seg[1] = SegD{o.Wh, o.Wl, o.XTh, o.XTl, Nr, Nr, (int)Nr};
+  const int64_t tiles = (Dr / TL2::BN) * (Nr / TL2::BM);
   int splits = pick_splits(tiles, 2 * Nr / (64 / (int64_t)sizeof(T)));
   while (splits > 1 && (size_t)splits * N * D * sizeof(CT) > a.part_bytes) splits >>= 1;
+  const dim3 grid((unsigned)(Dr / TL2::BN), (unsigned)(Nr / TL2::BM), (unsigned)splits);
   if (splits == 1) {
-    EpiG<128> e{a.s, a.Xt64, D, a.wpart, ntn, a.a0, a.G, D, (int)N, (int)D};
+    EpiG<TL2::BM> e{a.s, a.Xt64, D, a.wpart, ntn, a.a0, a.G, D, (int)N, (int)D};
     clk_begin(CLK_GEMM2, st);
-    gemm_dma_kernel<T, 128, 128, 4, X3, EpiG<128>><<<dim3(Dr / 128, ntn), 256, 0, st>>>(g, e);
+    gemm_dma_kernel<T, TL2, X3, EpiG<TL2::BM>><<<grid, TL2::NT, 0, st>>>(g, e);
     LAUNCHCHK();
     clk_end(CLK_GEMM2, st);
   } else {
     EpiPart<CT> e{static_cast<CT*>(a.part), D, (int)N, (int)D};
     clk_begin(CLK_GEMM2, st);
-    gemm_dma_kernel<T, 128, 128, 4, X3, EpiPart<CT>><<<dim3(Dr / 128, ntn, splits), 256, 0, st>>>(g, e);
+    gemm_dma_kernel<T, TL2, X3, EpiPart<CT>><<<grid, TL2::NT, 0, st>>>(g, e);
     LAUNCHCHK();
     clk_end(CLK_GEMM2, st);
     clk_begin(CLK_GEMM2_REDUCE, st);
@@ -440,6 +463,32 @@ static void mvm_gemms_dma(const MvmArgs& a, int64_t Nr, int64_t Dk, int64_t Dr, 
                                       a.a0, a.G);
     LAUNCHCHK();
     clk_end(CLK_GEMM2_REDUCE, st);
+  }
+}
+
+// Tile shapes: 64 x 64 (GEMM 1) and 128 x 128 (GEMM 2) by 4 waves for small
+// N, where the grid would otherwise leave CUs idle.  For large N the BF16
+// GEMMs are bound by operand traffic into LDS, so larger tiles by 8 waves
+// cut the bytes per flop (the split-BF16 wave sub-tile stays 64 x 64 to fit
+// the registers); FP32 and FP64 stay at 128 x 128, which measured faster.
+typedef DmaTile<64, 64, 2, 2, 4> TileM;        // GEMM 1 of small N: 4x more workgroups
+typedef DmaTile<128, 128, 2, 2, 4> TileS;
+typedef DmaTile<256, 256, 2, 4, 4> TileL;      // 128 x 64 per wave
+typedef DmaTile<256, 128, 4, 2, 3> TileLX3;    // 64 x 64 per wave, hi/lo operands
+constexpr int64_t kLargeN = 4096;
+
+template <typename T, bool X3, typename CT>
+static void mvm_gemms_for(const MvmArgs& a, int64_t Nr, int64_t Dk, int64_t Dr, const DmaOps& o, hipStream_t st,
+                          hipEvent_t* ev) {
+  if (a.Nt < kLargeN) {
+    mvm_gemms_dma<T, X3, CT, TileM, TileS>(a, Nr, Dk, Dr, o, st, ev);
+  } else if constexpr (X3) {
+    mvm_gemms_dma<T, X3, CT, TileLX3, TileLX3>(a, Nr, Dk, Dr, o, st, ev);
+  } else if constexpr (sizeof(T) == 2) {
+    mvm_gemms_dma<T, X3, CT, TileL, TileL>(a, Nr, Dk, Dr, o, st, ev);
+  } else {
+    // FP32 / FP64: MFMA-bound already at 128 x 128 (measured faster than the large tiles)
+    mvm_gemms_dma<T, X3, CT, TileS, TileS>(a, Nr, Dk, Dr, o, st, ev);
   }
 }
 
@@ -453,10 +502,10 @@ static void ensure_work(ffk_system* s, int prec, hipStream_t st) {
     w.s.alloc(D * 8);
     w.spart.alloc((int64_t)cdiv(N, GT) * D * 8);
     w.G.alloc(N * D * 8);
-    w.wpart.alloc(N * (rup(N, 128) / 128) * 8);
+    w.wpart.alloc(N * (pad_rows(N) / 64) * 8);   // one partial per GEMM 1 tile column (tiles >= 64 wide)
     w.part.alloc(part_budget(N, D));
   }
-  const int64_t Nr = rup(N, 128), Dk = rup(D, 64), Dr = rup(D, 128);
+  const int64_t Nr = pad_rows(N), Dk = rup(D, 64), Dr = pad_rows(D);
   // padding rows/columns stay zero: the kernels write only the valid part
   auto zeroed = [&](DBuf& b, int64_t bytes) {
     b.alloc(bytes);
@@ -492,7 +541,7 @@ void kernel_mvm_ev(ffk_system* s, const double* v, double* y, double shift, int 
   const int64_t N = s->N, D = s->D;
   const int M = s->M;
   MvmWork& w = s->work;
-  const int64_t Nr = rup(N, 128), ldu = rup(D, 64);
+  const int64_t Nr = pad_rows(N), ldu = rup(D, 64);
   const int nblk = cdiv(N, GT);
   const size_t shm = (size_t)2 * GT * 3 * M * sizeof(double);
   double* pd = w.pd.as<double>();
@@ -518,28 +567,34 @@ void kernel_mvm_ev(ffk_system* s, const double* v, double* y, double shift, int 
   MvmArgs a{N, N, D, s->a0, s->Xc.as<double>(), pd, w.s.as<double>(), w.wpart.as<double>(), w.G.as<double>(),
             w.part.get(), w.part.bytes()};
   CoeffSet& cs = s->coef[prec];
-  const int ntn = (int)(Nr / 128);
-  const int64_t Dk = rup(D, 64), Dr = rup(D, 128);
+  const int64_t Dk = rup(D, 64), Dr = pad_rows(D);
+  DmaOps o{};
+  o.dAh = cs.dA_hi.get();
+  o.Bc = cs.B.get();
   if (prec == FFK_FP64) {
-    EpiW<double, 128> e{cs.B.as<double>(), Nr, pd, w.Wn64.as<double>(), Nr, a.wpart, ntn, (int)N, (int)N};
-    mvm_gemms_dma<double, false, double>(a, Nr, Dk, Dr, s->Xp64.get(), nullptr, s->XpT64.get(), nullptr,
-                                         w.U64.get(), nullptr, w.UT64.get(), nullptr, cs.dA_hi.get(), nullptr,
-                                         w.Wn64.get(), nullptr, e, st, ev);
+    o.Xh = s->Xp64.get(); o.XTh = s->XpT64.get();
+    o.Uh = w.U64.get(); o.UTh = w.UT64.get();
+    o.Wh = w.Wn64.get();
+    mvm_gemms_for<double, false, double>(a, Nr, Dk, Dr, o, st, ev);
   } else if (prec == FFK_FP32) {
-    EpiW<float, 128> e{cs.B.as<float>(), Nr, pd, w.Wn32.as<float>(), Nr, a.wpart, ntn, (int)N, (int)N};
-    mvm_gemms_dma<float, false, float>(a, Nr, Dk, Dr, s->Xp32.get(), nullptr, s->XpT32.get(), nullptr, w.U32.get(),
-                                       nullptr, w.UT32.get(), nullptr, cs.dA_hi.get(), nullptr, w.Wn32.get(),
-                                       nullptr, e, st, ev);
-  } else if (prec == FFK_BF16X3) {
-    EpiWbf<128, true> e{cs.B.as<float>(), Nr, pd, w.Wnh.as<bf16_t>(), w.Wnl.as<bf16_t>(), a.wpart, ntn, (int)N};
-    mvm_gemms_dma<bf16_t, true, float>(a, Nr, Dk, Dr, s->Xch.get(), s->Xcl.get(), s->XcTh.get(), s->XcTl.get(),
-                                       w.Uh.get(), w.Ul.get(), w.UTh.get(), w.UTl.get(), cs.dA_hi.get(),
-                                       cs.dA_lo.get(), w.Wnh.get(), w.Wnl.get(), e, st, ev);
+    o.Xh = s->Xp32.get(); o.XTh = s->XpT32.get();
+    o.Uh = w.U32.get(); o.UTh = w.UT32.get();
+    o.Wh = w.Wn32.get();
+    mvm_gemms_for<float, false, float>(a, Nr, Dk, Dr, o, st, ev);
   } else {
-    EpiWbf<128, false> e{cs.B.as<float>(), Nr, pd, w.Wnh.as<bf16_t>(), nullptr, a.wpart, ntn, (int)N};
-    mvm_gemms_dma<bf16_t, false, float>(a, Nr, Dk, Dr, s->Xch.get(), nullptr, s->XcTh.get(), nullptr, w.Uh.get(),
-                                        nullptr, w.UTh.get(), nullptr, cs.dA_hi.get(), nullptr, w.Wnh.get(),
-                                        nullptr, e, st, ev);
+    const bool x3 = prec == FFK_BF16X3;
+    o.Xh = s->Xch.get(); o.XTh = s->XcTh.get();
+    o.Uh = w.Uh.get(); o.UTh = w.UTh.get();
+    o.Wh = w.Wnh.get();
+    if (x3) {
+      o.Xl = s->Xcl.get(); o.XTl = s->XcTl.get();
+      o.Ul = w.Ul.get(); o.UTl = w.UTl.get();
+      o.dAl = cs.dA_lo.get();
+      o.Wl = w.Wnl.get();
+      mvm_gemms_for<bf16_t, true, float>(a, Nr, Dk, Dr, o, st, ev);
+    } else {
+      mvm_gemms_for<bf16_t, false, float>(a, Nr, Dk, Dr, o, st, ev);
+    }
   }
   mark(ev, 4, st);
   const int tb = M <= 64 ? 64 : 128;

@@ -361,35 +361,43 @@ template <int C> __device__ inline int lt_col(int lane) {
 }
 
 // part[blockIdx.y][c] = sum over the block's rows i of A[i + c lda] x[i]
-// (only rows i >= c when TRI: A lower-triangular).  Block: 256 lanes x V rows,
-// C columns.
-template <typename TA, int C, bool TRI>
+// (only rows i >= c when TRI: A lower-triangular).  Block: 256 lanes x RR
+// row chunks of V rows, C columns; each lane issues all RR x C of its loads
+// before using any (RR = 2 measured fastest on the tall L).
+template <typename TA, int C, int RR, bool TRI>
 __global__ __launch_bounds__(256) void k_lt_part(const TA* __restrict__ A, int64_t nrow, int64_t lda, int64_t ncol,
                                                  const double* __restrict__ x, double* __restrict__ part) {
   constexpr int V = Vec16<TA>::V;
   __shared__ double red[4][C];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int64_t i = (int64_t)blockIdx.y * (256 * V) + (int64_t)threadIdx.x * V;
   const int64_t c0 = (int64_t)blockIdx.x * C;
   double acc[C];
 #pragma unroll
   for (int c = 0; c < C; ++c) acc[c] = 0.0;
-  if (i < nrow) {   // i + V <= lda: i is a multiple of V and lda of 64
-    double xr[V];
+  uint4 a[RR][C];
+  double xr[RR][V];
 #pragma unroll
-    for (int e = 0; e < V; ++e) xr[e] = (i + e < nrow) ? x[i + e] : 0.0;
-    uint4 a[C];
+  for (int h = 0; h < RR; ++h) {
+    // i + V <= lda whenever i < nrow: i is a multiple of V and lda of 64
+    const int64_t i = (int64_t)blockIdx.y * (256 * RR * V) + (int64_t)(h * 256 + threadIdx.x) * V;
+#pragma unroll
+    for (int e = 0; e < V; ++e) xr[h][e] = (i + e < nrow) ? x[i + e] : 0.0;
 #pragma unroll
     for (int c = 0; c < C; ++c) {
       const int64_t col = c0 + c;
-      a[c] = (col < ncol && !(TRI && i + V <= col)) ? load16(A + col * lda + i) : make_uint4(0, 0, 0, 0);
+      a[h][c] = (i < nrow && col < ncol && !(TRI && i + V <= col)) ? load16(A + col * lda + i)
+                                                                     : make_uint4(0, 0, 0, 0);
     }
+  }
+#pragma unroll
+  for (int h = 0; h < RR; ++h) {
+    const int64_t i = (int64_t)blockIdx.y * (256 * RR * V) + (int64_t)(h * 256 + threadIdx.x) * V;
 #pragma unroll
     for (int c = 0; c < C; ++c) {
       double v[V];
-      Vec16<TA>::expand(a[c], v);
+      Vec16<TA>::expand(a[h][c], v);
 #pragma unroll
-      for (int e = 0; e < V; ++e) acc[c] += ((TRI && i + e < c0 + c) ? 0.0 : v[e]) * xr[e];
+      for (int e = 0; e < V; ++e) acc[c] += ((TRI && i + e < c0 + c) ? 0.0 : v[e]) * xr[h][e];
     }
   }
   wave_reduce_cols<C>(acc, lane);
@@ -476,14 +484,17 @@ __global__ void k_finish_n(const double* __restrict__ part, int nb, int64_t stri
   out[i] = r ? alpha * (r[i] - sm) : sm;
 }
 
+constexpr int LT_RR = 2;       // row chunks per lane of the transposed product
 template <typename TA>
-static int64_t lt_rows() { return 256 * Vec16<TA>::V; }
+static int64_t lt_rows() { return 256 * LT_RR * Vec16<TA>::V; }   // rows per block, transposed product
+template <typename TA>
+static int64_t ln_rows() { return 256 * Vec16<TA>::V; }           // rows per block, direct product
 
 // workspace (doubles) needed by gemv_t / gemv_n for an nrow x ncol operand
 template <typename TA, bool TRI>
 static int64_t gemv_work(int64_t nrow, int64_t ncol) {
   const int64_t wt = cdiv(nrow, lt_rows<TA>()) * ncol;
-  const int64_t wn = cdiv(ncol, ln_cols<TRI>()) * (cdiv(nrow, lt_rows<TA>()) * lt_rows<TA>());
+  const int64_t wn = cdiv(ncol, ln_cols<TRI>()) * (cdiv(nrow, ln_rows<TA>()) * ln_rows<TA>());
   return std::max(wt, wn);
 }
 
@@ -492,7 +503,7 @@ static void gemv_t(const TA* A, int64_t nrow, int64_t lda, int64_t ncol, const d
                    hipStream_t st, int clk = -1) {
   const int nb = cdiv(nrow, lt_rows<TA>());
   if (clk >= 0) clk_begin(clk, st);
-  k_lt_part<TA, LT_COLS, TRI><<<dim3(cdiv(ncol, LT_COLS), nb), 256, 0, st>>>(A, nrow, lda, ncol, x, part);
+  k_lt_part<TA, LT_COLS, LT_RR, TRI><<<dim3(cdiv(ncol, LT_COLS), nb), 256, 0, st>>>(A, nrow, lda, ncol, x, part);
   LAUNCHCHK();
   if (clk >= 0) clk_end(clk, st);
   k_sum_rows<<<cdiv(ncol, 256), 256, 0, st>>>(part, nb, ncol, y);
@@ -503,8 +514,8 @@ template <typename TA, bool TRI = false>
 static void gemv_n(const TA* A, int64_t nrow, int64_t lda, int64_t ncol, const double* t, const double* r,
                    double alpha, double* out, double* part, hipStream_t st, int clk = -1) {
   const int nb = cdiv(ncol, ln_cols<TRI>());
-  const int gx = cdiv(nrow, lt_rows<TA>());
-  const int64_t stride = (int64_t)gx * lt_rows<TA>();
+  const int gx = cdiv(nrow, ln_rows<TA>());
+  const int64_t stride = (int64_t)gx * ln_rows<TA>();
   if (clk >= 0) clk_begin(clk, st);
   k_ln_part<TA, TRI><<<dim3(gx, nb), 256, 0, st>>>(A, nrow, lda, ncol, t, part, stride);
   LAUNCHCHK();
