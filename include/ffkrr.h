@@ -181,6 +181,18 @@ ffk_status ffk_nystrom_select(ffk_ctx* ctx, ffk_system* sys, ffk_select strategy
  * FFK_BF16X3 is FFK_ERR_ARG. */
 ffk_status ffk_precond_build(ffk_ctx* ctx, ffk_system* sys, const int64_t* idx_dev, int64_t k,
                              double lambda, ffk_precision store_L, ffk_precond** out, void* stream);
+/* ffk_precond_build with flags.  FFK_BUILD_LOWMEM (store_L must be FFK_FP32)
+ * computes each 64-column panel of L in FP64 from the earlier columns as
+ * stored in FP32 and keeps only the FP32 factor: n k 4 bytes instead of the
+ * n k 12 of an FP64 factor plus its FP32 copy.  The factor then differs from
+ * the rounded FP64 one by FP32 rounding in the panel updates (the
+ * preconditioner stays exactly SPD, its core built from the stored L).
+ * ffk_precond_build picks this build by itself for FFK_FP32 storage when the
+ * FP64 factor and its copy would not fit in the device's free memory. */
+enum { FFK_BUILD_LOWMEM = 1 };
+ffk_status ffk_precond_build_ex(ffk_ctx* ctx, ffk_system* sys, const int64_t* idx_dev, int64_t k,
+                                double lambda, ffk_precision store_L, int32_t flags, ffk_precond** out,
+                                void* stream);
 void ffk_precond_free(ffk_precond* P);
 /* k requested, k_eff kept, bytes of device memory held. */
 ffk_status ffk_precond_info(const ffk_precond* P, int64_t* k, int64_t* k_eff, int64_t* bytes);
@@ -206,6 +218,9 @@ typedef struct {
   int32_t timing;         /* 1: time MVM / preconditioner / vector phases with events */
   double switch_below;    /* > 0: FP64 products while the updated residual is above
                              switch_below |F|, then `prec` (0: `prec` from the start) */
+  int32_t progress_every; /* > 0: print one line to stderr every so many iterations
+                             (iteration, updated and true residual, precision) */
+  int32_t reserved;       /* 0 */
 } ffk_pcg_opts;
 
 typedef struct {

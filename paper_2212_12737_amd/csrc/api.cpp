@@ -228,19 +228,26 @@ ffk_status ffk_nystrom_select(ffk_ctx* ctx, ffk_system* s, ffk_select strategy, 
   });
 }
 
-ffk_status ffk_precond_build(ffk_ctx* ctx, ffk_system* s, const int64_t* idx, int64_t k, double lambda,
-                             ffk_precision store_L, ffk_precond** out, void* stream) {
+ffk_status ffk_precond_build_ex(ffk_ctx* ctx, ffk_system* s, const int64_t* idx, int64_t k, double lambda,
+                                ffk_precision store_L, int32_t flags, ffk_precond** out, void* stream) {
   if (!ctx || !s || !out) return FFK_ERR_ARG;
   *out = nullptr;
   return guarded(ctx, [&]() {
     require(idx != nullptr, "precond_build: idx is null");
     require(k >= 1 && k <= s->n, "precond_build: need 1 <= k <= n");
     require(lambda > 0.0 && std::isfinite(lambda), "precond_build: lambda must be > 0");
+    require((flags & ~FFK_BUILD_LOWMEM) == 0, "precond_build: unknown flags");
+    require(!(flags & FFK_BUILD_LOWMEM) || store_L == FFK_FP32, "precond_build: the low-memory build stores FP32");
     check_indices(idx, k, s->n, S(stream), "precond_build");
     bool dropped = false;
-    *out = precond_build(s, idx, k, lambda, (int)store_L, &dropped, S(stream));
+    *out = precond_build(s, idx, k, lambda, (int)store_L, (flags & FFK_BUILD_LOWMEM) != 0, &dropped, S(stream));
     return dropped ? FFK_WARN_RANK_DROPPED : FFK_OK;
   });
+}
+
+ffk_status ffk_precond_build(ffk_ctx* ctx, ffk_system* s, const int64_t* idx, int64_t k, double lambda,
+                             ffk_precision store_L, ffk_precond** out, void* stream) {
+  return ffk_precond_build_ex(ctx, s, idx, k, lambda, store_L, 0, out, stream);
 }
 
 void ffk_precond_free(ffk_precond* P) { delete P; }

@@ -240,6 +240,13 @@ struct View64 {
 };
 void gemm64(int M, int N, int K, double alpha, View64 A, View64 B, double beta, double* C,
             int64_t scm, int64_t scn, bool lower_only, hipStream_t st);
+// The same product with FP32 operands, FP64 arithmetic and output.
+struct View32 {
+  const float* p;
+  int64_t s0, s1;
+};
+void gemm64_in32(int M, int N, int K, double alpha, View32 A, View32 B, double beta, double* C, int64_t scm,
+                 int64_t scn, hipStream_t st);
 // Lower Cholesky in place of the n x n column-major matrix A (lda). Returns the
 // index of the first failing pivot or -1.
 int64_t potrf_lower(double* A, int64_t n, int64_t lda, hipStream_t st);
@@ -265,8 +272,11 @@ void leverage_estimate(ffk_system* sys, const int64_t* pilot, int64_t s, double 
 // kept (host, k) receives which columns survived.
 int64_t icd_forced(ffk_system* sys, const int64_t* idx, int64_t k, double shift, double* L, int64_t ld,
                    std::vector<char>* kept, hipStream_t st);
+// lowmem: build L straight into FP32 storage (one FP64 panel at a time) instead
+// of an FP64 factor that is rounded afterwards; chosen automatically when the
+// FP64 factor would not fit next to its FP32 copy.
 ffk_precond* precond_build(ffk_system* sys, const int64_t* idx, int64_t k, double lambda,
-                           int store, bool* dropped, hipStream_t st);
+                           int store, bool lowmem, bool* dropped, hipStream_t st);
 void precond_apply(const ffk_precond* P, const double* r, double* z, hipStream_t st);
 
 // pcg.hip
@@ -291,6 +301,16 @@ void block_log_scores(const double* tau, int64_t N, int M, float* y, hipStream_t
 // GEMM tile edge, so tiles never read past an array.
 constexpr int64_t kRowPad = 256;
 inline int64_t pad_rows(int64_t n) { return (n + kRowPad - 1) / kRowPad * kRowPad; }
+
+// Fragment-major layout of the BF16 GEMM operands.  An operand with rows
+// padded to 16 and K padded to 32 is stored as 1 KB blocks, one per (16-row
+// group, 32-wide K tile), blocks of a row group consecutive in K; inside a
+// block, the 16 bytes at offset 16 L hold row L % 16, K elements
+// 8 (L / 16) .. +7 -- exactly what lane L of a 16x16x32 MFMA reads.  One
+// contiguous 1 KB load per block then fills LDS in fragment order.
+__host__ __device__ inline int64_t frag_off(int64_t row, int64_t k, int64_t KT) {
+  return ((((row >> 4) * KT + (k >> 5)) << 9) | ((((k & 31) >> 3) << 4 | (row & 15)) << 3) | (k & 7));
+}
 
 // clock.cpp -- per-kernel event clocks (ids match ffk_clock in ffkrr.h)
 enum ClockId {

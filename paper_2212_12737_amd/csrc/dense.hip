@@ -49,6 +49,32 @@ void gemm64(int M, int N, int K, double alpha, View64 A, View64 B, double beta, 
   gemm64_dispatch(M, N, K, alpha, A, B, beta, C, scm, scn, lower_only, false, st);
 }
 
+template <bool AKC, bool BKC>
+static void gemm64_in32_t(int M, int N, int K, double alpha, View32 A, View32 B, double beta, double* C, int64_t scm,
+                          int64_t scn, hipStream_t st) {
+  ScalarArgs<float> g{};
+  g.M = M;
+  g.N = N;
+  g.nseg = 1;
+  g.seg[0] = SegS<float>{A.p, A.s0, A.s1, B.p, B.s0, B.s1, K};
+  EpiAxpby<double> e{C, scm, scn, M, N, alpha, beta};
+  dim3 grid(cdiv(N, 128), cdiv(M, 128));
+  gemm_scalar_kernel<double, 128, 128, 16, AKC, BKC, EpiAxpby<double>, float><<<grid, 256, 0, st>>>(g, e);
+  LAUNCHCHK();
+}
+
+void gemm64_in32(int M, int N, int K, double alpha, View32 A, View32 B, double beta, double* C, int64_t scm,
+                 int64_t scn, hipStream_t st) {
+  if (M <= 0 || N <= 0) return;
+  const bool akc = (A.s1 == 1), bkc = (B.s1 == 1);
+  require(akc || A.s0 == 1, "gemm64_in32: A needs a unit stride");
+  require(bkc || B.s0 == 1, "gemm64_in32: B needs a unit stride");
+  if (akc && bkc) gemm64_in32_t<true, true>(M, N, K, alpha, A, B, beta, C, scm, scn, st);
+  else if (akc) gemm64_in32_t<true, false>(M, N, K, alpha, A, B, beta, C, scm, scn, st);
+  else if (bkc) gemm64_in32_t<false, true>(M, N, K, alpha, A, B, beta, C, scm, scn, st);
+  else gemm64_in32_t<false, false>(M, N, K, alpha, A, B, beta, C, scm, scn, st);
+}
+
 void gemm64_alower(int M, int N, int K, double alpha, View64 A, View64 B, double beta, double* C, int64_t scm,
                    int64_t scn, hipStream_t st) {
   gemm64_dispatch(M, N, K, alpha, A, B, beta, C, scm, scn, false, true, st);

@@ -130,6 +130,8 @@ void descriptor_build(ffk_system* s, const double* R, hipStream_t st) {
 
 // hi/lo split of a rows x cols FP64 matrix into padded bf16 arrays
 // (rows_p x ld_out); entries outside rows x cols are written as zero.
+// hi (+ lo) split of a rows x cols FP64 matrix into a rows_p x ld_out
+// operand in fragment-major layout (K = ld_out), zero outside.
 __global__ void k_split_pad(const double* __restrict__ a, int64_t rows, int64_t cols, int64_t lda,
                             int64_t rows_p, int64_t ld_out, bf16_t* __restrict__ hi,
                             bf16_t* __restrict__ lo) {
@@ -139,8 +141,9 @@ __global__ void k_split_pad(const double* __restrict__ a, int64_t rows, int64_t 
   float x = 0.f;
   if (r < rows && c < cols) x = (float)a[r * lda + c];
   const bf16_t h = f2bf(x);
-  hi[e] = h;
-  if (lo) lo[e] = f2bf(x - bf2f(h));
+  const int64_t o = frag_off(r, c, ld_out / 32);
+  hi[o] = h;
+  if (lo) lo[o] = f2bf(x - bf2f(h));
 }
 
 // FP32 copy of a rows x cols FP64 matrix into a padded rows_p x ld_out array.
@@ -152,8 +155,9 @@ __global__ void k_f32_pad(const double* __restrict__ a, int64_t rows, int64_t co
   out[e] = (r < rows && c < cols) ? (float)a[r * lda + c] : 0.f;
 }
 
-// Transposed hi/lo split: a is rows x cols (lda); output cols_p x ld_out with
-// out[c][r] = split(a[r][c]), zero outside.  64 x 64 tiles through LDS.
+// Transposed hi/lo split: a is rows x cols (lda); output cols_p x ld_out
+// (fragment-major, K = ld_out) with out[c][r] = split(a[r][c]), zero
+// outside.  64 x 64 tiles through LDS.
 __global__ void k_split_transpose(const double* __restrict__ a, int64_t rows, int64_t cols, int64_t lda,
                                   int64_t cols_p, int64_t ld_out, bf16_t* __restrict__ hi,
                                   bf16_t* __restrict__ lo) {
@@ -170,8 +174,9 @@ __global__ void k_split_transpose(const double* __restrict__ a, int64_t rows, in
     if (c < cols_p && r < ld_out) {
       const float x = tile[tx][i];
       const bf16_t h = f2bf(x);
-      hi[c * ld_out + r] = h;
-      if (lo) lo[c * ld_out + r] = f2bf(x - bf2f(h));
+      const int64_t o = frag_off(c, r, ld_out / 32);
+      hi[o] = h;
+      if (lo) lo[o] = f2bf(x - bf2f(h));
     }
   }
 }

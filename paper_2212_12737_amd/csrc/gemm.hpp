@@ -387,8 +387,9 @@ template <> struct DmaMfma<double> {
 
 // Operand segment of the pipelined engine: K-contiguous arrays of T whose row
 // count is padded to the tile and whose leading dimension (in elements) and K
-// are multiples of 64 bytes; padding is zero.  The lo arrays are used only in
-// the split-BF16 mode.
+// are multiples of 64 bytes; padding is zero.  BF16 operands are in the
+// fragment-major layout (frag_off, with K tiles of 32) and ignore lda/ldb.
+// The lo arrays are used only in the split-BF16 mode.
 struct SegD {
   const void *Ah, *Al;
   const void *Bh, *Bl;
@@ -443,11 +444,17 @@ __global__ __launch_bounds__(TL::NT) void gemm_dma_kernel(DmaArgs g, Epi epi) {
 #pragma unroll
     for (int j = 0; j < TN; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
 
-  // lane L of a group load: row L%16, 16-byte chunk L/16
+  // Row-major operands (FP32, FP64): lane L of a group load takes row L%16,
+  // 16-byte chunk L/16.  BF16 operands are fragment-major (frag_off): the
+  // 1 KB block of a (row group, K tile) is contiguous, lane L takes bytes
+  // 16 L .. 16 L + 15, and whole cache lines move per load.
+  constexpr bool FRAG = sizeof(T) == 2;
   const int lrow = lane & 15, lchunk = lane >> 4;
   auto issue = [&](int t) {
     const SegD& sg = (t < t0) ? g.seg[0] : g.seg[1];
-    const int64_t k0 = (int64_t)(t < t0 ? t : t - t0) * BK + lchunk * (16 / (int)sizeof(T));
+    const int64_t tk = (t < t0 ? t : t - t0);
+    const int64_t k0 = tk * BK + lchunk * (16 / (int)sizeof(T));
+    const int64_t KT = sg.K / BK;
     char* st = smem + (t % S) * STAGE_BYTES;
 #pragma unroll
     for (int h = 0; h < NARR; ++h) {
@@ -456,13 +463,16 @@ __global__ __launch_bounds__(TL::NT) void gemm_dma_kernel(DmaArgs g, Epi epi) {
 #pragma unroll
       for (int q = 0; q < QA; ++q) {
         const int grp = wave * QA + q;
-        dma16(A + (int64_t)(m0 + grp * 16 + lrow) * sg.lda + k0, st + h * A_BYTES + grp * GROUP_BYTES);
+        const T* src = FRAG ? A + (((int64_t)(m0 / 16 + grp) * KT + tk) * 512 + lane * 8)
+                            : A + (int64_t)(m0 + grp * 16 + lrow) * sg.lda + k0;
+        dma16(src, st + h * A_BYTES + grp * GROUP_BYTES);
       }
 #pragma unroll
       for (int q = 0; q < QB; ++q) {
         const int grp = wave * QB + q;
-        dma16(B + (int64_t)(n0 + grp * 16 + lrow) * sg.ldb + k0,
-              st + NARR * A_BYTES + h * B_BYTES + grp * GROUP_BYTES);
+        const T* src = FRAG ? B + (((int64_t)(n0 / 16 + grp) * KT + tk) * 512 + lane * 8)
+                            : B + (int64_t)(n0 + grp * 16 + lrow) * sg.ldb + k0;
+        dma16(src, st + NARR * A_BYTES + h * B_BYTES + grp * GROUP_BYTES);
       }
     }
   };
@@ -490,6 +500,9 @@ __global__ __launch_bounds__(TL::NT) void gemm_dma_kernel(DmaArgs g, Epi epi) {
       bh[j] = *reinterpret_cast<const u4*>(st + NARR * A_BYTES + (wn * TN + j) * GROUP_BYTES + lane * 16);
       if (X3) bl[X3 ? j : 0] = *reinterpret_cast<const u4*>(st + NARR * A_BYTES + B_BYTES + (wn * TN + j) * GROUP_BYTES + lane * 16);
     }
+    // all fragment reads are issued before the first MFMA: left to itself the
+    // scheduler interleaves them in pairs, each behind a full LDS-latency wait
+    __builtin_amdgcn_sched_barrier(0);
     // FP64: slice-outer order, so consecutive instructions update different
     // accumulators (measured faster); FP32 and BF16: block-outer order
     if (sizeof(T) != 8) {

@@ -23,8 +23,9 @@ static int64_t rup(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
 constexpr int GT = 16;
 
 // MODE: 0 = FP64, 1 = FP32, 2 = split BF16 (hi in U/UT, lo in Ul/UTl).
-// U is written row-major with leading dimension ldu; UT (if not null) is the
-// transposed copy with leading dimension ldut.  Padding is left untouched.
+// U is written row-major with leading dimension ldu (BF16: fragment-major
+// with K = ldu); UT (if not null) is the transposed copy with leading
+// dimension ldut (BF16: fragment-major, K = ldut).  Padding is left untouched.
 template <int MODE>
 __global__ __launch_bounds__(256) void k_jv_tile(const double* __restrict__ R, const int* __restrict__ pairs,
                                                  const double* __restrict__ v, const double* __restrict__ Xc,
@@ -65,11 +66,12 @@ __global__ __launch_bounds__(256) void k_jv_tile(const double* __restrict__ R, c
         const int64_t o = (g0 + gl) * ldu + d;
         if (MODE == 0) static_cast<double*>(U)[o] = u;
         if (MODE == 1) static_cast<float*>(U)[o] = (float)u;
-        if (MODE == 2) {
+        if (MODE == 2) {   // fragment-major, K = ldu
           const float f = (float)u;
           const bf16_t h = f2bf(f);
-          static_cast<bf16_t*>(U)[o] = h;
-          static_cast<bf16_t*>(Ul)[o] = f2bf(f - bf2f(h));
+          const int64_t of = frag_off(g0 + gl, d, ldu / 32);
+          static_cast<bf16_t*>(U)[of] = h;
+          static_cast<bf16_t*>(Ul)[of] = f2bf(f - bf2f(h));
         }
       }
       cs += u;
@@ -83,11 +85,12 @@ __global__ __launch_bounds__(256) void k_jv_tile(const double* __restrict__ R, c
           const int64_t o = d * ldut + g0 + gl;
           if (MODE == 0) static_cast<double*>(UT)[o] = ug[gl];
           if (MODE == 1) static_cast<float*>(UT)[o] = (float)ug[gl];
-          if (MODE == 2) {
+          if (MODE == 2) {   // fragment-major, K = ldut
             const float f = (float)ug[gl];
             const bf16_t h = f2bf(f);
-            static_cast<bf16_t*>(UT)[o] = h;
-            static_cast<bf16_t*>(UTl)[o] = f2bf(f - bf2f(h));
+            const int64_t of = frag_off(d, g0 + gl, ldut / 32);
+            static_cast<bf16_t*>(UT)[of] = h;
+            static_cast<bf16_t*>(UTl)[of] = f2bf(f - bf2f(h));
           }
         }
     }
@@ -233,8 +236,9 @@ struct EpiWbf {
           const float pdc = c < N ? (float)pd[c] : 0.f;
           const float w = Bc[(int64_t)r * ld + c] * (acc[i][j][v] - pdc);
           const bf16_t h = f2bf(-w);
-          Wh[(int64_t)r * ld + c] = h;
-          if (X3) Wl[(int64_t)r * ld + c] = f2bf(-w - bf2f(h));
+          const int64_t o = frag_off(r, c, ld / 32);   // -W: fragment-major, K = ld
+          Wh[o] = h;
+          if (X3) Wl[o] = f2bf(-w - bf2f(h));
           rs += (double)w;
         }
         rs += __shfl_xor(rs, 1);

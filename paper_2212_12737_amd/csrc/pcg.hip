@@ -19,6 +19,7 @@
 // A breakdown (p^T q <= 0) under a reduced-precision product escalates like a
 // stagnating refresh when `escalate` is set.
 #include <chrono>
+#include <cstdio>
 
 #include "common.hpp"
 
@@ -230,6 +231,12 @@ ffk_status pcg_solve(ffk_system* s, const ffk_precond* P, const double* F, doubl
       switch_iter = it;
     }
     if (rep && rep->hist_host && hist_len < rep->hist_cap) rep->hist_host[hist_len++] = rel_upd;
+    if (o->progress_every > 0 && it % o->progress_every == 0) {
+      static const char* names[4] = {"fp64", "fp32", "bf16", "bf16x3"};
+      fprintf(stderr, "pcg it %lld  updated residual %.3e  last true residual %.3e  products %s\n", (long long)it,
+              rel_upd, rel_true, names[hi_phase ? FFK_FP64 : cur]);
+      fflush(stderr);
+    }
     const bool candidate = rel_upd <= o->tol;
     if (candidate || periodic) {
       const double tr = true_residual();

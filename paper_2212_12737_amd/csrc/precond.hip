@@ -35,6 +35,15 @@ __global__ void k_gather_rows(const double* L, int64_t ld, const int64_t* idx, i
   G[e] = L[idx[c] + j * ld];
 }
 
+// The same from FP32 storage.
+__global__ void k_gather_rows32(const float* L, int64_t ld, const int64_t* idx, int nb, int64_t m0, float* G) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)nb * m0) return;
+  const int c = (int)(e / m0);
+  const int64_t j = e % m0;
+  G[e] = L[idx[c] + j * ld];
+}
+
 // Factor the nb x nb pivot block T[c][c'] = panel[idx[c], c'] with drops and
 // invert it.  Outputs: Lb (PB x PB row-major, lower; dropped columns zero),
 // Linv (PB x PB row-major) = inverse of Lb with a unit diagonal put at dropped
@@ -101,10 +110,12 @@ __global__ __launch_bounds__(256) void k_panel_chol(const double* Lp, int64_t ld
 
 // Exact zeros at earlier pivot rows and the exact pivot value on the diagonal;
 // dropped columns are cleared entirely.
+// (The panel's column c is at L + (m0 - col0 + c) ld: col0 = 0 when L is the
+// whole factor, col0 = m0 when L is a panel buffer of its own.)
 __global__ void k_panel_fix(double* L, int64_t n, int64_t ld, const int64_t* idx, const unsigned char* kept,
-                            int64_t m0, int nb, const double* Lb) {
+                            int64_t m0, int nb, const double* Lb, int64_t col0) {
   const int c = blockIdx.x;
-  double* col = L + (m0 + c) * ld;
+  double* col = L + (m0 - col0 + c) * ld;
   if (!kept[m0 + c]) {
     for (int64_t i = threadIdx.x; i < n; i += blockDim.x) col[i] = 0.0;
     return;
@@ -141,7 +152,53 @@ int64_t icd_forced(ffk_system* s, const int64_t* idx, int64_t k, double shift, d
     gemm64((int)n, nb, nb, 1.0, View64{Lp, 1, ld}, View64{Linv.as<double>(), PB, 1}, 0.0, Lp, 1, ld, false, st);
     k_set_kept<<<1, PB, 0, st>>>(dropped.as<unsigned char>(), nb, kept.as<unsigned char>() + m0);
     LAUNCHCHK();
-    k_panel_fix<<<nb, 256, 0, st>>>(L, n, ld, idx, kept.as<unsigned char>(), m0, nb, Lb.as<double>());
+    k_panel_fix<<<nb, 256, 0, st>>>(L, n, ld, idx, kept.as<unsigned char>(), m0, nb, Lb.as<double>(), 0);
+    LAUNCHCHK();
+  }
+  std::vector<char> hk(std::max<int64_t>(k, 1));
+  HIPCHK(hipMemcpyAsync(hk.data(), kept.get(), k, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  int64_t keff = 0;
+  for (int64_t j = 0; j < k; ++j) keff += hk[j] ? 1 : 0;
+  if (kept_out) kept_out->assign(hk.begin(), hk.begin() + k);
+  return keff;
+}
+
+__global__ void k_cols_to_f32(const double* P, int64_t ld, int64_t n, int nb, float* L32) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= ld * nb) return;
+  L32[e] = (float)P[e];
+}
+
+// icd_forced with the factor kept in FP32: each panel is computed in FP64
+// (raw columns, update by the earlier FP32 columns with FP64 accumulation,
+// pivot-block factorization and drops) and then stored in FP32.  Needs
+// n k 4 + n 64 8 bytes instead of n k 8.
+static int64_t icd_forced_f32(ffk_system* s, const int64_t* idx, int64_t k, float* L32, int64_t ld,
+                              std::vector<char>* kept_out, hipStream_t st) {
+  const int64_t n = s->n;
+  const double thr = 1e-12 * max_diag(s, st);
+  DBuf P64(ld * PB * 8), G((int64_t)PB * std::max<int64_t>(k, 1) * 4), Lb(PB * PB * 8), Linv(PB * PB * 8),
+      dropped(PB), kept(std::max<int64_t>(k, 1));
+  double* Lp = P64.as<double>();
+  for (int64_t m0 = 0; m0 < k; m0 += PB) {
+    const int nb = (int)std::min<int64_t>(PB, k - m0);
+    HIPCHK(hipMemsetAsync(Lp, 0, ld * PB * 8, st));
+    kernel_columns(s, idx + m0, nb, Lp, ld, 0.0, st);
+    if (m0 > 0) {
+      k_gather_rows32<<<cdiv((int64_t)nb * m0, 256), 256, 0, st>>>(L32, ld, idx + m0, nb, m0, G.as<float>());
+      LAUNCHCHK();
+      gemm64_in32((int)n, nb, (int)m0, -1.0, View32{L32, 1, ld}, View32{G.as<float>(), m0, 1}, 1.0, Lp, 1, ld, st);
+    }
+    k_panel_chol<<<1, 256, 0, st>>>(Lp, ld, idx + m0, nb, thr, Lb.as<double>(), Linv.as<double>(),
+                                    dropped.as<unsigned char>());
+    LAUNCHCHK();
+    gemm64((int)n, nb, nb, 1.0, View64{Lp, 1, ld}, View64{Linv.as<double>(), PB, 1}, 0.0, Lp, 1, ld, false, st);
+    k_set_kept<<<1, PB, 0, st>>>(dropped.as<unsigned char>(), nb, kept.as<unsigned char>() + m0);
+    LAUNCHCHK();
+    k_panel_fix<<<nb, 256, 0, st>>>(Lp, n, ld, idx, kept.as<unsigned char>(), m0, nb, Lb.as<double>(), m0);
+    LAUNCHCHK();
+    k_cols_to_f32<<<cdiv(ld * nb, 256), 256, 0, st>>>(Lp, ld, n, nb, L32 + m0 * ld);
     LAUNCHCHK();
   }
   std::vector<char> hk(std::max<int64_t>(k, 1));
@@ -205,8 +262,19 @@ static void gram_cols(const TI* L, int64_t n, int64_t ld, int64_t k, double* C, 
 
 int64_t precond_work_doubles(int64_t n, int64_t ld, int64_t keff, int store);
 
-ffk_precond* precond_build(ffk_system* s, const int64_t* idx, int64_t k, double lambda, int store, bool* dropped_any,
-                           hipStream_t st) {
+// compact the kept columns to the front (in order; a column only moves left)
+static void compact_columns(char* L, int64_t ld, int64_t esize, const std::vector<char>& kept, hipStream_t st) {
+  int64_t w = 0;
+  for (size_t j = 0; j < kept.size(); ++j) {
+    if (!kept[j]) continue;
+    if (w != (int64_t)j)
+      HIPCHK(hipMemcpyAsync(L + w * ld * esize, L + (int64_t)j * ld * esize, ld * esize, hipMemcpyDeviceToDevice, st));
+    ++w;
+  }
+}
+
+ffk_precond* precond_build(ffk_system* s, const int64_t* idx, int64_t k, double lambda, int store, bool lowmem,
+                           bool* dropped_any, hipStream_t st) {
   require(store == FFK_FP64 || store == FFK_FP32 || store == FFK_BF16,
           "precond_build: store_L must be FFK_FP64, FFK_FP32 or FFK_BF16");
   const int64_t n = s->n;
@@ -218,28 +286,35 @@ ffk_precond* precond_build(ffk_system* s, const int64_t* idx, int64_t k, double 
   P->k = k;
   P->lambda = lambda;
   P->store = store;
-  DBuf L64(ld * k * 8);
-  HIPCHK(hipMemsetAsync(L64.get(), 0, ld * k * 8, st));
-  std::vector<char> kept;
-  const int64_t keff = icd_forced(s, idx, k, 0.0, L64.as<double>(), ld, &kept, st);
-  *dropped_any = keff < k;
-  // compact the kept columns to the front (in order; a column only moves left)
-  {
-    int64_t w = 0;
-    for (int64_t j = 0; j < k; ++j) {
-      if (!kept[j]) continue;
-      if (w != j)
-        HIPCHK(hipMemcpyAsync(L64.as<double>() + w * ld, L64.as<double>() + j * ld, ld * 8, hipMemcpyDeviceToDevice, st));
-      ++w;
-    }
+  if (store == FFK_FP32 && !lowmem) {
+    size_t freeb = 0, total = 0;
+    HIPCHK(hipMemGetInfo(&freeb, &total));
+    lowmem = (double)ld * k * 12.0 > 0.9 * (double)freeb;   // FP64 factor + its FP32 copy
   }
+  std::vector<char> kept;
+  DBuf L64;
+  int64_t keff;
+  if (lowmem) {
+    require(store == FFK_FP32, "precond_build: the low-memory build stores L in FP32");
+    P->L.alloc(ld * k * 4);
+    keff = icd_forced_f32(s, idx, k, P->L.as<float>(), ld, &kept, st);
+    compact_columns(P->L.as<char>(), ld, 4, kept, st);
+  } else {
+    L64.alloc(ld * k * 8);
+    HIPCHK(hipMemsetAsync(L64.get(), 0, ld * k * 8, st));
+    keff = icd_forced(s, idx, k, 0.0, L64.as<double>(), ld, &kept, st);
+    compact_columns(L64.as<char>(), ld, 8, kept, st);
+  }
+  *dropped_any = keff < k;
   P->k_eff = keff;
   const int64_t ke = std::max<int64_t>(keff, 1);
   const int64_t ldf = pad64(ke);
   P->ldf = ldf;
   DBuf core(ldf * ke * 8);
   HIPCHK(hipMemsetAsync(core.get(), 0, ldf * ke * 8, st));
-  if (store == FFK_FP64) {
+  if (lowmem) {
+    if (keff > 0) gram_cols<float>(P->L.as<float>(), n, ld, keff, core.as<double>(), ldf, st);
+  } else if (store == FFK_FP64) {
     if (keff > 0) gram_cols<double>(L64.as<double>(), n, ld, keff, core.as<double>(), ldf, st);
     P->L = std::move(L64);
   } else if (store == FFK_FP32) {

@@ -34,7 +34,8 @@ class FfkError(RuntimeError):
 class PcgOpts(ctypes.Structure):
     _fields_ = [("lam", ctypes.c_double), ("tol", ctypes.c_double), ("max_iter", ctypes.c_int64),
                 ("prec", ctypes.c_int32), ("refresh_every", ctypes.c_int32), ("escalate", ctypes.c_int32),
-                ("flexible", ctypes.c_int32), ("timing", ctypes.c_int32), ("switch_below", ctypes.c_double)]
+                ("flexible", ctypes.c_int32), ("timing", ctypes.c_int32), ("switch_below", ctypes.c_double),
+                ("progress_every", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class PcgReport(ctypes.Structure):
@@ -70,6 +71,7 @@ _SIGS = {
     "ffk_kernel_diag": (I32, [P, P, P, P]),
     "ffk_nystrom_select": (I32, [P, P, I32, I64, DBL, U64, I64, P, P, ctypes.POINTER(I64), P, P]),
     "ffk_precond_build": (I32, [P, P, P, I64, DBL, I32, PP, P]),
+    "ffk_precond_build_ex": (I32, [P, P, P, I64, DBL, I32, I32, PP, P]),
     "ffk_precond_free": (None, [P]),
     "ffk_precond_info": (I32, [P, ctypes.POINTER(I64), ctypes.POINTER(I64), ctypes.POINTER(I64)]),
     "ffk_precond_apply": (I32, [P, P, P, P, P]),
@@ -274,12 +276,16 @@ class Precond:
             self.h = None
 
 
+BUILD_LOWMEM = 1
+
+
 def precond_build(ctx: Context, sys: System, idx: torch.Tensor, lam: float, store: int = FP64,
-                  stream=None) -> Precond:
+                  lowmem: bool = False, stream=None) -> Precond:
     idx = idx.to(device=ctx.torch_device, dtype=torch.int64).contiguous()
     h = ctypes.c_void_p()
-    st = ctx.check(lib().ffk_precond_build(ctx.h, sys.h, _ptr(idx), idx.numel(), lam, store, ctypes.byref(h),
-                                           _stream(stream)), "precond_build")
+    flags = BUILD_LOWMEM if lowmem else 0
+    st = ctx.check(lib().ffk_precond_build_ex(ctx.h, sys.h, _ptr(idx), idx.numel(), lam, store, flags,
+                                              ctypes.byref(h), _stream(stream)), "precond_build")
     return Precond(ctx, h, st)
 
 
@@ -320,10 +326,11 @@ class Report:
 def pcg_solve(ctx: Context, sys: System, P: Precond | None, F: torch.Tensor, lam: float, tol: float = 1e-6,
               max_iter: int = 0, prec: int = FP64, refresh_every: int = 10, escalate: bool = True,
               flexible: bool = False, timing: bool = False, hist_cap: int = 0, alpha: torch.Tensor | None = None,
-              switch_below: float = 0.0, stream=None):
+              switch_below: float = 0.0, progress_every: int = 0, stream=None):
     if alpha is None:
         alpha = torch.empty(sys.n, dtype=torch.float64, device=ctx.torch_device)
-    o = PcgOpts(lam, tol, max_iter, prec, refresh_every, int(escalate), int(flexible), int(timing), switch_below)
+    o = PcgOpts(lam, tol, max_iter, prec, refresh_every, int(escalate), int(flexible), int(timing), switch_below,
+                int(progress_every), 0)
     rep = PcgReport()
     hist = (ctypes.c_double * hist_cap)() if hist_cap > 0 else None
     if hist is not None:

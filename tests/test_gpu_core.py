@@ -240,6 +240,33 @@ def test_precond_apply_storage_formats(ffk, ctx, apply_case, store):
     assert float(r @ z) > 0
 
 
+def test_precond_low_memory_build(ffk, ctx, apply_case):
+    """FP32-storage build (panels in FP64, earlier columns read in FP32).
+
+    The first panel has no earlier columns, so it is the oracle's factor
+    rounded to FP32.  Later columns carry the FP32 rounding of the earlier
+    ones through the Schur-complement updates, amplified where the remaining
+    pivots are small, so they are compared through L L^T; the apply must
+    still invert the operator built from the stored factor exactly."""
+    s, idx, Lo, lam, r = apply_case
+    S = ffk.descriptor_build(ctx, dev(s.R), SIGMA)
+    P = ffk.precond_build(ctx, S, dev(idx, torch.int64), lam, store=ffk.FP32, lowmem=True)
+    assert P.k_eff == Lo.shape[1]
+    Ls = host(ffk.precond_export(ctx, P, S.n))
+    d0 = np.abs(Ls[:, :64] - Lo[:, :64])
+    assert np.all(d0 <= 2.0 ** -23 * np.abs(Lo[:, :64]) + 1e-10 * np.abs(Lo).max())
+    LLo = Lo @ Lo.T
+    dev_LL = np.abs(Ls @ Ls.T - LLo).max() / np.abs(LLo).max()
+    z = host(ffk.precond_apply(ctx, P, dev(r)))
+    dev_z = relerr(z, osv.woodbury(Lo, lam)(r))
+    print("low-memory build: L L^T deviation %.2e, apply deviation %.2e" % (dev_LL, dev_z), flush=True)
+    assert dev_LL <= 1e-5
+    a, b = Ls @ (Ls.T @ z), lam * z
+    scale = (np.linalg.norm(a) + np.linalg.norm(b)) / np.linalg.norm(r)
+    assert relerr(a + b, r) <= 1e-9 * max(scale, 1.0)
+    assert float(r @ z) > 0
+
+
 def test_precond_drops_dependent_columns(ffk, ctx):
     s = system(5, 8, 305)
     S = ffk.descriptor_build(ctx, dev(s.R), SIGMA)
