@@ -194,6 +194,7 @@ struct ffk_precond {
   int32_t store = FFK_FP64;
   ffk::DBuf L;              // n x k column-major (double or float)
   ffk::DBuf Finv;           // k x k column-major lower-triangular inverse of F = chol(core)
+  ffk::DBuf FinvT;          // its transpose (upper triangle), same layout
   ffk::DBuf y, t1, t;       // k-vectors
   ffk::DBuf work;           // partial sums of the split GEMVs
   int64_t bytes = 0;
@@ -257,6 +258,20 @@ void trtri_lower(double* A, int64_t n, int64_t lda, hipStream_t st);
 constexpr int kRedParts = 1024;
 void dot64(const double* a, const double* b, int64_t n, double* part, double* out_dev, hipStream_t st);
 void reduce_max64(const double* a, int64_t n, double* part, double* out_dev, hipStream_t st);
+// Kernels that fuse a dot product into an elementwise pass run fused_parts(n)
+// blocks of 256 lanes over a grid-stride loop, reduce each block with
+// block_sum256 into part[block], and finish with sum_parts64 (fixed order).
+int fused_parts(int64_t n);
+void sum_parts64(const double* part, int np, double* out_dev, hipStream_t st);
+__device__ inline double block_sum256(double v, double* sh /* 256 doubles of LDS */) {
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  return sh[0];
+}
 
 // select.hip
 void select_uniform(const ffk_system* sys, int64_t k, uint64_t seed, int64_t* idx, hipStream_t st);
@@ -278,6 +293,9 @@ int64_t icd_forced(ffk_system* sys, const int64_t* idx, int64_t k, double shift,
 ffk_precond* precond_build(ffk_system* sys, const int64_t* idx, int64_t k, double lambda,
                            int store, bool lowmem, bool* dropped, hipStream_t st);
 void precond_apply(const ffk_precond* P, const double* r, double* z, hipStream_t st);
+// z = M^-1 r and *rz_dev = r^T z (part: kRedParts doubles of workspace)
+void precond_apply_dot(const ffk_precond* P, const double* r, double* z, double* part, double* rz_dev,
+                       hipStream_t st);
 
 // pcg.hip
 ffk_status pcg_solve(ffk_system* sys, const ffk_precond* P, const double* F, double* alpha,

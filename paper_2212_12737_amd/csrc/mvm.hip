@@ -10,6 +10,8 @@
 // because sum_j W_ij d_ij = w_i x_i - (W X)_i and a_ij = a(0) + dA_ij.  The
 // constant a(0) part and the row sums are kept in FP64; only the two products
 // run in the requested precision.
+#include <type_traits>
+
 #include "gemm.hpp"
 
 namespace ffk {
@@ -212,48 +214,79 @@ struct EpiW {
   }
 };
 
-// BF16 variant: coefficient in FP32, -W stored as bf16 hi (+lo), all padded
-// entries written (they are zero because B is zero there).
-template <int BM, bool X3>
-struct EpiWbf {
-  const float* Bc; int64_t ld;   // B and Wn share the padded leading dimension
+// FP32 and BF16 products: GEMM 1 runs transposed, P^T = U X_c^T (A = U,
+// B = X_c).  In their MFMA output layout lane l holds rows 4(l/16)+v of a
+// 16x16 block, which are then four consecutive columns c0..c0+3 of one row r
+// of W: B is read as one 16-byte vector, -W is written as one vector (FP32
+// row-major; BF16 hi and lo in fragment order, 8 bytes each) and the row sum
+// of W is mostly lane-local.  The coefficient B is FP32; FP32 products form W
+// in FP64 arithmetic, BF16 products in FP32.  All padded entries are written
+// (zero, as B is zero there).  Row-sum partials: one per row of W and tile of
+// its columns (GEMM 1 tile row).
+template <typename CT, bool X3>
+struct EpiWT {
+  const float* Bc; int64_t ld;   // B and -W share the padded leading dimension
   const double* pd;
-  bf16_t* Wh; bf16_t* Wl;
-  double* wpart; int ntn;
+  CT* Wh; CT* Wl;
+  double* wpart; int nparts;
   int N;
   template <typename T, int TM, int TN, class Acc>
   __device__ void run(const Acc (&acc)[TM][TN], const FragCoord& f, char* smem) const {
-    double* red = reinterpret_cast<double*>(smem);   // [wave columns][BM]
+    static_assert(sizeof(CT) == 4 || sizeof(CT) == 2, "FP32 or BF16 storage");
+    typedef typename std::conditional<sizeof(CT) == 4, double, float>::type MT;
+    double* red = reinterpret_cast<double*>(smem);   // [wave rows][BN]
+    const int WM = (blockDim.x >> 6) / f.nwcol, BN = f.nwcol * 16 * TN;
+    const int wm = (f.wm0 - f.m0) / (16 * TM);
+    double rs[TN];
 #pragma unroll
-    for (int i = 0; i < TM; ++i)
+    for (int j = 0; j < TN; ++j) rs[j] = 0.0;
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int r = f.row(i, v);
-        double rs = 0.0;
+    for (int i = 0; i < TM; ++i) {
+      const int c0 = f.row(i, 0);
+      MT p[4];
 #pragma unroll
-        for (int j = 0; j < TN; ++j) {
-          const int c = f.col(j);
-          const float pdc = c < N ? (float)pd[c] : 0.f;
-          const float w = Bc[(int64_t)r * ld + c] * (acc[i][j][v] - pdc);
-          const bf16_t h = f2bf(-w);
-          const int64_t o = frag_off(r, c, ld / 32);   // -W: fragment-major, K = ld
-          Wh[o] = h;
-          if (X3) Wl[o] = f2bf(-w - bf2f(h));
-          rs += (double)w;
+      for (int v = 0; v < 4; ++v) p[v] = c0 + v < N ? (MT)pd[c0 + v] : (MT)0;
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        const int r = f.col(j);
+        const f4 b = *reinterpret_cast<const f4*>(Bc + (int64_t)r * ld + c0);
+        MT w[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          w[v] = (MT)b[v] * ((MT)acc[i][j][v] - p[v]);
+          rs[j] += (double)w[v];
         }
-        rs += __shfl_xor(rs, 1);
-        rs += __shfl_xor(rs, 2);
-        rs += __shfl_xor(rs, 4);
-        rs += __shfl_xor(rs, 8);
-        if ((f.lane & 15) == 0) red[f.wcol * BM + (r - f.m0)] = rs;
+        if constexpr (sizeof(CT) == 4) {
+          *reinterpret_cast<f4*>(Wh + (int64_t)r * ld + c0) = f4{(float)-w[0], (float)-w[1], (float)-w[2], (float)-w[3]};
+        } else {
+          uint32_t h[4], l[4];
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const bf16_t hv = f2bf((float)-w[v]);
+            h[v] = hv;
+            l[v] = X3 ? f2bf((float)-w[v] - bf2f(hv)) : 0u;
+          }
+          const int64_t o = frag_off(r, c0, ld / 32);   // c0 % 4 == 0: 8-byte aligned
+          *reinterpret_cast<uint2*>(Wh + o) = make_uint2(h[0] | h[1] << 16, h[2] | h[3] << 16);
+          if (X3) *reinterpret_cast<uint2*>(Wl + o) = make_uint2(l[0] | l[1] << 16, l[2] | l[3] << 16);
+        }
       }
+    }
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+      double s = rs[j];
+      s += __shfl_xor(s, 16);
+      s += __shfl_xor(s, 32);
+      if (f.lane < 16) red[wm * BN + (f.col(j) - f.n0)] = s;
+    }
     __syncthreads();
-    for (int t = threadIdx.x; t < BM; t += blockDim.x) {
-      const int r = f.m0 + t;
+    const int tm = f.m0 / (16 * TM * WM);
+    for (int t = threadIdx.x; t < BN; t += blockDim.x) {
+      const int r = f.n0 + t;
       if (r < N) {
         double a = 0.0;
-        for (int q = 0; q < f.nwcol; ++q) a += red[q * BM + t];
-        wpart[(int64_t)r * ntn + f.tn] = a;
+        for (int q = 0; q < WM; ++q) a += red[q * BN + t];
+        wpart[(int64_t)r * nparts + tm] = a;
       }
     }
   }
@@ -418,20 +451,58 @@ struct DmaOps {
   void *Wh, *Wl;                     // -W
 };
 
+// K splits for GEMM 2.  A grid smaller than the workgroup slots of the GPU
+// takes the fixed rule of pick_splits.  A larger grid takes the split count
+// that minimises the estimated time: ceil(tiles s / slots) rounds of 1/s of
+// the K loop each, plus the split-K partials written and read back once.
+// Without it, 553 tiles of 256 x 256 on 256 slots run 3 rounds for 2.16
+// rounds of work.  Rates per CU are the engine's measured main-loop rates
+// (BF16 ~1.2 PFLOP/s, FP32 ~115 TFLOP/s, FP64 ~50 TFLOP/s over 256 CUs), and
+// HBM ~5 TB/s for the partials; only their ratio matters.
+template <typename T, bool X3, class TL, typename CT>
+static int gemm2_splits(int64_t tiles, int64_t ktiles, int64_t N, int64_t D) {
+  static int per_cu = 0, cus = 0;
+  if (per_cu == 0) {
+    int nb = 0, dev = 0;
+    HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, gemm_dma_kernel<T, TL, X3, EpiPart<CT>>, TL::NT, 0));
+    HIPCHK(hipGetDevice(&dev));
+    HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    per_cu = nb > 0 ? nb : 1;
+  }
+  const int64_t slots = (int64_t)cus * per_cu;
+  if (tiles < slots) return pick_splits(tiles, ktiles);
+  const double rate_cu = (sizeof(T) == 2 ? 1.2e15 : sizeof(T) == 4 ? 1.15e14 : 5.0e13) / 256.0;
+  const double t_tile = 2.0 * TL::BM * TL::BN * (double)ktiles * (64 / sizeof(T)) * (X3 ? 3 : 1) / rate_cu;
+  const double t_part = 2.0 * (double)N * D * sizeof(CT) / 5.0e12;
+  int best = 1;
+  double bt = 0.0;
+  for (int s = 1; s <= 16 && (int64_t)s * 4 <= ktiles; ++s) {
+    const double t = (double)((tiles * s + slots - 1) / slots) * per_cu * t_tile / s + (s > 1 ? s * t_part : 0.0);
+    if (s == 1 || t < 0.98 * bt) {
+      bt = t;
+      best = s;
+    }
+  }
+  return best;
+}
+
 template <typename T, bool X3, typename CT, class TL1, class TL2>
 static void mvm_gemms_dma(const MvmArgs& a, int64_t Nr, int64_t Dk, int64_t Dr, const DmaOps& o, hipStream_t st,
                           hipEvent_t* ev) {
   const int64_t N = a.Nt, D = a.D;
-  const int ntn = (int)(Nr / TL1::BN);   // GEMM 1 tile columns = row-sum partials per row
+  // FP32 and BF16: GEMM 1 computes P^T (EpiWT), so the row-sum partials of W
+  // are per GEMM 1 tile row; FP64 keeps P = X_c U^T and per tile column.
+  constexpr bool kTrans = sizeof(T) != 8;
+  const int ntn = (int)(Nr / (kTrans ? TL1::BM : TL1::BN));   // row-sum partials per row of W
   {
     DmaArgs g{};
     g.nseg = 1;
-    g.seg[0] = SegD{o.Xh, o.Xl, o.Uh, o.Ul, Dk, Dk, (int)Dk};
+    g.seg[0] = kTrans ? SegD{o.Uh, o.Ul, o.Xh, o.Xl, Dk, Dk, (int)Dk} : SegD{o.Xh, o.Xl, o.Uh, o.Ul, Dk, Dk, (int)Dk};
     const dim3 grid((unsigned)(Nr / TL1::BN), (unsigned)(Nr / TL1::BM));
     clk_begin(CLK_GEMM1, st);
-    if constexpr (sizeof(T) == 2) {
-      EpiWbf<TL1::BM, X3> e{static_cast<const float*>(o.Bc), Nr, a.pd, static_cast<bf16_t*>(o.Wh),
-                            static_cast<bf16_t*>(o.Wl), a.wpart, ntn, (int)N};
+    if constexpr (kTrans) {
+      EpiWT<T, X3> e{static_cast<const float*>(o.Bc), Nr, a.pd, static_cast<T*>(o.Wh), static_cast<T*>(o.Wl),
+                     a.wpart, ntn, (int)N};
       gemm_dma_kernel<T, TL1, X3, decltype(e)><<<grid, TL1::NT, 0, st>>>(g, e);
     } else {
       EpiW<T, TL1::BM> e{static_cast<const T*>(o.Bc), Nr, a.pd, static_cast<T*>(o.Wh), Nr, a.wpart, ntn, (int)N,
@@ -447,7 +518,7 @@ static void mvm_gemms_dma(const MvmArgs& a, int64_t Nr, int64_t Dk, int64_t Dr, 
   g.seg[0] = SegD{o.dAh, o.dAl, o.UTh, o.UTl, Nr, Nr, (int)Nr};
   g.seg[1] = SegD{o.Wh, o.Wl, o.XTh, o.XTl, Nr, Nr, (int)Nr};
   const int64_t tiles = (Dr / TL2::BN) * (Nr / TL2::BM);
-  int splits = pick_splits(tiles, 2 * Nr / (64 / (int64_t)sizeof(T)));
+  int splits = gemm2_splits<T, X3, TL2, CT>(tiles, 2 * Nr / (64 / (int64_t)sizeof(T)), N, D);
   while (splits > 1 && (size_t)splits * N * D * sizeof(CT) > a.part_bytes) splits >>= 1;
   const dim3 grid((unsigned)(Dr / TL2::BN), (unsigned)(Nr / TL2::BM), (unsigned)splits);
   if (splits == 1) {

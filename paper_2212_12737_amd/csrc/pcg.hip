@@ -27,13 +27,23 @@ namespace ffk {
 
 enum { S_RHO0 = 0, S_RHO1 = 1, S_PAP = 2, S_RR = 3, S_ZQ = 4, S_FF = 5, S_TMP = 6, NSC = 8 };
 
-__global__ void k_axpy2(double* __restrict__ x, double* __restrict__ r, const double* __restrict__ p,
-                        const double* __restrict__ q, const double* __restrict__ sc, int rho, int64_t n) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+// x += g p, r -= g q with g = rho / p^T q, and the block partials of |r|^2 of
+// the updated r (fused_parts grid)
+__global__ __launch_bounds__(256) void k_axpy2_rr(double* __restrict__ x, double* __restrict__ r,
+                                                  const double* __restrict__ p, const double* __restrict__ q,
+                                                  const double* __restrict__ sc, int rho, int64_t n,
+                                                  double* __restrict__ rr_part) {
+  __shared__ double sh[256];
   const double g = sc[rho] / sc[S_PAP];
-  x[i] += g * p[i];
-  r[i] -= g * q[i];
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    x[i] += g * p[i];
+    const double ri = r[i] - g * q[i];
+    r[i] = ri;
+    acc += ri * ri;
+  }
+  const double s = block_sum256(acc, sh);
+  if (threadIdx.x == 0) rr_part[blockIdx.x] = s;
 }
 
 // pn = z + beta p (out of place, so that a speculative update can be redone)
@@ -111,6 +121,7 @@ ffk_status pcg_solve(ffk_system* s, const ffk_precond* P, const double* F, doubl
   double* SC = sc.as<double>();
   double* PART = part.as<double>();
   const int nb = cdiv(n, 256);
+  const int np_fused = fused_parts(n);
   s->ctx->host_scratch.ensure(64);
   double* hs = s->ctx->host_scratch.as<double>();
   struct Ev {
@@ -180,9 +191,14 @@ ffk_status pcg_solve(ffk_system* s, const ffk_precond* P, const double* F, doubl
   };
   // Next direction from the current r: z = M^-1 r, rho_new = r^T z, pn = z + beta p.
   auto next_direction = [&](int rho_new) {
-    apply_prec(R, Z);
+    if (P) {
+      Timer tm(timing, st, &t_prec);
+      precond_apply_dot(P, R, Z, PART, SC + rho_new, st);
+    } else {
+      apply_prec(R, Z);
+      dot64(R, Z, n, PART, SC + rho_new, st);
+    }
     Timer tm(timing, st, &t_vec);
-    dot64(R, Z, n, PART, SC + rho_new, st);
     if (o->flexible) dot64(Z, Q, n, PART, SC + S_ZQ, st);
     k_update_p<<<nb, 256, 0, st>>>(Pn, Pv, Z, SC, rho, rho_new, o->flexible, n);
     LAUNCHCHK();
@@ -201,9 +217,9 @@ ffk_status pcg_solve(ffk_system* s, const ffk_precond* P, const double* F, doubl
     {
       Timer tm(timing, st, &t_vec);
       dot64(Pv, Q, n, PART, SC + S_PAP, st);
-      k_axpy2<<<nb, 256, 0, st>>>(alpha, R, Pv, Q, SC, rho, n);
+      k_axpy2_rr<<<np_fused, 256, 0, st>>>(alpha, R, Pv, Q, SC, rho, n, PART);
       LAUNCHCHK();
-      dot64(R, R, n, PART, SC + S_RR, st);
+      sum_parts64(PART, np_fused, SC + S_RR, st);
       HIPCHK(hipMemcpyAsync(hs, SC + S_PAP, 16, hipMemcpyDeviceToHost, st));
       HIPCHK(hipEventRecord(done.e, st));
     }

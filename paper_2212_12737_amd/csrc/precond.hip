@@ -226,6 +226,18 @@ __global__ void k_zero_upper(double* A, int64_t k, int64_t ld) {
   const int64_t r = e % ld, c = e / ld;
   if (r < c) A[e] = 0.0;
 }
+// B = A^T for column-major k x k matrices with leading dimension ld (the
+// padding rows of B are left as they are)
+__global__ void k_transpose_sq(const double* __restrict__ A, int64_t k, int64_t ld, double* __restrict__ B) {
+  __shared__ double tile[32][33];
+  const int64_t r0 = (int64_t)blockIdx.x * 32, c0 = (int64_t)blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 256 threads: 32 x 8
+  for (int q = ty; q < 32; q += 8)
+    if (r0 + tx < k && c0 + q < k) tile[q][tx] = A[(r0 + tx) + (c0 + q) * ld];
+  __syncthreads();
+  for (int q = ty; q < 32; q += 8)
+    if (c0 + tx < k && r0 + q < k) B[(c0 + tx) + (r0 + q) * ld] = tile[tx][q];
+}
 __global__ void k_add_diag(double* C, int64_t k, int64_t ld, double lam) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < k) C[i + i * ld] += lam;
@@ -342,19 +354,27 @@ ffk_precond* precond_build(ffk_system* s, const int64_t* idx, int64_t k, double 
     k_zero_upper<<<cdiv(ldf * keff, 256), 256, 0, st>>>(core.as<double>(), keff, ldf);
     LAUNCHCHK();
   }
+  P->FinvT.alloc(ldf * ke * 8);
+  HIPCHK(hipMemsetAsync(P->FinvT.get(), 0, ldf * ke * 8, st));
+  if (keff > 0) {
+    k_transpose_sq<<<dim3(cdiv(keff, 32), cdiv(keff, 32)), 256, 0, st>>>(core.as<double>(), keff, ldf,
+                                                                          P->FinvT.as<double>());
+    LAUNCHCHK();
+  }
   P->Finv = std::move(core);
   P->y.alloc(ldf * 8);
   P->t1.alloc(ldf * 8);
   P->t.alloc(ldf * 8);
   P->work.alloc(precond_work_doubles(n, ld, ke, store) * 8);
-  P->bytes = (int64_t)(P->L.bytes() + P->Finv.bytes() + P->work.bytes() + 3 * ldf * 8);
+  P->bytes = (int64_t)(P->L.bytes() + P->Finv.bytes() + P->FinvT.bytes() + P->work.bytes() + 3 * ldf * 8);
   HIPCHK(hipStreamSynchronize(st));
   return P.release();
 }
 
 // ----------------------------------------------------------------- apply ----
-// The four products of the apply are memory-bound GEMVs over column-major
-// matrices whose leading dimension is a multiple of 64 with zero padding.
+// The two products of the apply with L are memory-bound GEMVs over a
+// column-major matrix whose leading dimension is a multiple of 64 with zero
+// padding.
 // Every lane issues 16-byte loads (2 doubles, 4 floats or 8 bfloat16 of one
 // column), all of a lane's loads for a tile of columns back to back, and
 // accumulates in FP64.  Partial results of the 2-D grid are combined by a
@@ -398,11 +418,9 @@ template <typename TA> __device__ inline uint4 load16(const TA* p) {
 
 constexpr int LT_COLS = 16;    // columns per block of the transposed product
 constexpr int LN_UNROLL = 16;  // loads in flight per lane in the direct product
-// columns per block of the direct product: wide for the tall L (few partial
-// sums to combine), narrow for the k x k triangle (enough blocks to fill the GPU)
-template <bool TRI> constexpr int ln_cols() { return TRI ? 32 : 256; }
-static_assert(ln_cols<false>() % LN_UNROLL == 0 && ln_cols<false>() <= 256, "direct-product column tile");
-static_assert(ln_cols<true>() % LN_UNROLL == 0, "direct-product column tile");
+// columns per block of the direct product: wide, so few partial sums remain
+constexpr int LN_COLS = 256;
+static_assert(LN_COLS % LN_UNROLL == 0 && LN_COLS <= 256, "direct-product column tile");
 
 // Sum of v[0..C) over the 64 lanes of a wave, one column per lane group:
 // recursive halving (each exchange step hands half of the values to the
@@ -435,11 +453,11 @@ template <int C> __device__ inline int lt_col(int lane) {
   return c;
 }
 
-// part[blockIdx.y][c] = sum over the block's rows i of A[i + c lda] x[i]
-// (only rows i >= c when TRI: A lower-triangular).  Block: 256 lanes x RR
+// part[blockIdx.y][c] = sum over the block's rows i of A[i + c lda] x[i].
+// Block: 256 lanes x RR
 // row chunks of V rows, C columns; each lane issues all RR x C of its loads
 // before using any (RR = 2 measured fastest on the tall L).
-template <typename TA, int C, int RR, bool TRI>
+template <typename TA, int C, int RR>
 __global__ __launch_bounds__(256) void k_lt_part(const TA* __restrict__ A, int64_t nrow, int64_t lda, int64_t ncol,
                                                  const double* __restrict__ x, double* __restrict__ part) {
   constexpr int V = Vec16<TA>::V;
@@ -460,8 +478,7 @@ __global__ __launch_bounds__(256) void k_lt_part(const TA* __restrict__ A, int64
 #pragma unroll
     for (int c = 0; c < C; ++c) {
       const int64_t col = c0 + c;
-      a[h][c] = (i < nrow && col < ncol && !(TRI && i + V <= col)) ? load16(A + col * lda + i)
-                                                                     : make_uint4(0, 0, 0, 0);
+      a[h][c] = (i < nrow && col < ncol) ? load16(A + col * lda + i) : make_uint4(0, 0, 0, 0);
     }
   }
 #pragma unroll
@@ -472,7 +489,7 @@ __global__ __launch_bounds__(256) void k_lt_part(const TA* __restrict__ A, int64
       double v[V];
       Vec16<TA>::expand(a[h][c], v);
 #pragma unroll
-      for (int e = 0; e < V; ++e) acc[c] += ((TRI && i + e < c0 + c) ? 0.0 : v[e]) * xr[h][e];
+      for (int e = 0; e < V; ++e) acc[c] += v[e] * xr[h][e];
     }
   }
   wave_reduce_cols<C>(acc, lane);
@@ -497,14 +514,14 @@ __global__ void k_sum_rows(const double* __restrict__ part, int nb, int64_t ncol
   y[c] = a0 + a1;
 }
 
-// part[blockIdx.y][i] = sum over the block's columns c of A[i + c lda] t[c]
-// (only c <= i when TRI).  Block: 256 lanes x V rows, ln_cols<TRI>() columns.
-template <typename TA, bool TRI>
+// part[blockIdx.y][i] = sum over the block's columns c of A[i + c lda] t[c].
+// Block: 256 lanes x V rows, LN_COLS columns.
+template <typename TA>
 __global__ __launch_bounds__(256) void k_ln_part(const TA* __restrict__ A, int64_t nrow, int64_t lda, int64_t ncol,
                                                  const double* __restrict__ t, double* __restrict__ part,
                                                  int64_t stride) {
   constexpr int V = Vec16<TA>::V;
-  constexpr int CB = ln_cols<TRI>();
+  constexpr int CB = LN_COLS;
   __shared__ double ts[CB];
   const int64_t c0 = (int64_t)blockIdx.y * CB;
   const int nc = (int)(ncol - c0 < CB ? ncol - c0 : CB);
@@ -512,12 +529,7 @@ __global__ __launch_bounds__(256) void k_ln_part(const TA* __restrict__ A, int64
   __syncthreads();
   const int64_t i = (int64_t)blockIdx.x * (256 * V) + (int64_t)threadIdx.x * V;
   if (i >= nrow) return;
-  // a lower-triangular A has nothing in columns beyond the block's last row
-  int cend = nc;
-  if (TRI) {
-    const int64_t lim = i + V - c0;
-    cend = (int)(lim < 0 ? 0 : (lim < nc ? lim : nc));
-  }
+  const int cend = nc;
   double acc[V];
 #pragma unroll
   for (int e = 0; e < V; ++e) acc[e] = 0.0;
@@ -534,7 +546,7 @@ __global__ __launch_bounds__(256) void k_ln_part(const TA* __restrict__ A, int64
       double v[V];
       Vec16<TA>::expand(a[u], v);
 #pragma unroll
-      for (int e = 0; e < V; ++e) acc[e] += ((TRI && col > i + e) ? 0.0 : v[e]) * tc;
+      for (int e = 0; e < V; ++e) acc[e] += v[e] * tc;
     }
   }
   double* out = part + (int64_t)blockIdx.y * stride + i;
@@ -559,6 +571,41 @@ __global__ void k_finish_n(const double* __restrict__ part, int nb, int64_t stri
   out[i] = r ? alpha * (r[i] - sm) : sm;
 }
 
+// z_i = alpha (r_i - sum_b part[b][i]) and the block partials of r^T z
+// (fused_parts grid)
+__global__ __launch_bounds__(256) void k_finish_n_dot(const double* __restrict__ part, int nb, int64_t stride,
+                                                      int64_t nrow, const double* __restrict__ r, double alpha,
+                                                      double* __restrict__ z, double* __restrict__ rz_part) {
+  __shared__ double sh[256];
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < nrow; i += (int64_t)gridDim.x * 256) {
+    double a0 = 0.0, a1 = 0.0;
+    int b = 0;
+    for (; b + 2 <= nb; b += 2) {
+      a0 += part[(int64_t)b * stride + i];
+      a1 += part[(int64_t)(b + 1) * stride + i];
+    }
+    if (b < nb) a0 += part[(int64_t)b * stride + i];
+    const double zi = alpha * (r[i] - (a0 + a1));
+    z[i] = zi;
+    acc += r[i] * zi;
+  }
+  const double s = block_sum256(acc, sh);
+  if (threadIdx.x == 0) rz_part[blockIdx.x] = s;
+}
+__global__ __launch_bounds__(256) void k_scale_dot(const double* __restrict__ r, double a, int64_t n,
+                                                   double* __restrict__ z, double* __restrict__ rz_part) {
+  __shared__ double sh[256];
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    const double zi = a * r[i];
+    z[i] = zi;
+    acc += r[i] * zi;
+  }
+  const double s = block_sum256(acc, sh);
+  if (threadIdx.x == 0) rz_part[blockIdx.x] = s;
+}
+
 constexpr int LT_RR = 2;       // row chunks per lane of the transposed product
 template <typename TA>
 static int64_t lt_rows() { return 256 * LT_RR * Vec16<TA>::V; }   // rows per block, transposed product
@@ -566,61 +613,108 @@ template <typename TA>
 static int64_t ln_rows() { return 256 * Vec16<TA>::V; }           // rows per block, direct product
 
 // workspace (doubles) needed by gemv_t / gemv_n for an nrow x ncol operand
-template <typename TA, bool TRI>
+template <typename TA>
 static int64_t gemv_work(int64_t nrow, int64_t ncol) {
   const int64_t wt = cdiv(nrow, lt_rows<TA>()) * ncol;
-  const int64_t wn = cdiv(ncol, ln_cols<TRI>()) * (cdiv(nrow, ln_rows<TA>()) * ln_rows<TA>());
+  const int64_t wn = cdiv(ncol, LN_COLS) * (cdiv(nrow, ln_rows<TA>()) * ln_rows<TA>());
   return std::max(wt, wn);
 }
 
-template <typename TA, bool TRI = false>
+template <typename TA>
 static void gemv_t(const TA* A, int64_t nrow, int64_t lda, int64_t ncol, const double* x, double* y, double* part,
                    hipStream_t st, int clk = -1) {
   const int nb = cdiv(nrow, lt_rows<TA>());
   if (clk >= 0) clk_begin(clk, st);
-  k_lt_part<TA, LT_COLS, LT_RR, TRI><<<dim3(cdiv(ncol, LT_COLS), nb), 256, 0, st>>>(A, nrow, lda, ncol, x, part);
+  k_lt_part<TA, LT_COLS, LT_RR><<<dim3(cdiv(ncol, LT_COLS), nb), 256, 0, st>>>(A, nrow, lda, ncol, x, part);
   LAUNCHCHK();
   if (clk >= 0) clk_end(clk, st);
   k_sum_rows<<<cdiv(ncol, 256), 256, 0, st>>>(part, nb, ncol, y);
   LAUNCHCHK();
 }
 
-template <typename TA, bool TRI = false>
+template <typename TA>
 static void gemv_n(const TA* A, int64_t nrow, int64_t lda, int64_t ncol, const double* t, const double* r,
                    double alpha, double* out, double* part, hipStream_t st, int clk = -1) {
-  const int nb = cdiv(ncol, ln_cols<TRI>());
+  const int nb = cdiv(ncol, LN_COLS);
   const int gx = cdiv(nrow, ln_rows<TA>());
   const int64_t stride = (int64_t)gx * ln_rows<TA>();
   if (clk >= 0) clk_begin(clk, st);
-  k_ln_part<TA, TRI><<<dim3(gx, nb), 256, 0, st>>>(A, nrow, lda, ncol, t, part, stride);
+  k_ln_part<TA><<<dim3(gx, nb), 256, 0, st>>>(A, nrow, lda, ncol, t, part, stride);
   LAUNCHCHK();
   if (clk >= 0) clk_end(clk, st);
   k_finish_n<<<cdiv(nrow, 256), 256, 0, st>>>(part, nb, stride, nrow, r, alpha, out);
   LAUNCHCHK();
 }
 
+// The Woodbury core t = F^-T F^-1 y as two kernels of column dot products,
+// one block per output and no partial sums: s_j = (column j of F^-T) . y over
+// rows 0..j, then t_j = (column j of F^-1) . s over rows j..k-1.  Both
+// triangles are stored with zeros in the other half, so the 16-byte loads
+// start at an even row and the extra entries add zero; rows at or beyond k
+// are never read.  Ordinary (cached) loads: the 2 x 8 k^2 bytes can stay in
+// the last-level cache between iterations.
+template <bool FROM_DIAG>
+__global__ __launch_bounds__(256) void k_tri_dots(const double* __restrict__ A, int64_t lda, int64_t k,
+                                                  const double* __restrict__ x, double* __restrict__ out) {
+  __shared__ double red[4];
+  const int64_t j = blockIdx.x;
+  const int64_t lo = FROM_DIAG ? (j & ~(int64_t)1) : 0;
+  const int64_t hi = FROM_DIAG ? k : j + 1;
+  const double* col = A + j * lda;
+  double a0 = 0.0, a1 = 0.0;
+  // i is even, so i + 1 < k when k is even and i + 1 <= k < lda when k is
+  // odd: the second element of a load is inside the column
+  for (int64_t i = lo + 2 * (int64_t)threadIdx.x; i < hi; i += 512) {
+    const double2 v = *reinterpret_cast<const double2*>(col + i);
+    a0 += v.x * x[i];
+    if (i + 1 < hi) a1 += v.y * x[i + 1];
+  }
+  double acc = a0 + a1;
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) out[j] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
 template <typename TA>
-static void apply_t(const ffk_precond* P, const double* r, double* z, hipStream_t st) {
+static void apply_t(const ffk_precond* P, const double* r, double* z, hipStream_t st, double* rz_part = nullptr,
+                    double* rz = nullptr) {
   const TA* L = P->L.as<TA>();
   const int64_t n = P->n, k = P->k_eff;
   const double* F = P->Finv.as<double>();
   double* part = P->work.as<double>();
   gemv_t<TA>(L, n, P->ld, k, r, P->y.as<double>(), part, st, CLK_GEMV_T);
   clk_begin(CLK_CORE, st);
-  gemv_n<double, true>(F, k, P->ldf, k, P->y.as<double>(), nullptr, 1.0, P->t1.as<double>(), part, st);
-  gemv_t<double, true>(F, k, P->ldf, k, P->t1.as<double>(), P->t.as<double>(), part, st);
+  k_tri_dots<false><<<k, 256, 0, st>>>(P->FinvT.as<double>(), P->ldf, k, P->y.as<double>(),
+                                                 P->t1.as<double>());
+  LAUNCHCHK();
+  k_tri_dots<true><<<k, 256, 0, st>>>(F, P->ldf, k, P->t1.as<double>(), P->t.as<double>());
+  LAUNCHCHK();
   clk_end(CLK_CORE, st);
-  gemv_n<TA>(L, n, P->ld, k, P->t.as<double>(), r, 1.0 / P->lambda, z, part, st, CLK_GEMV_N);
+  if (!rz) {
+    gemv_n<TA>(L, n, P->ld, k, P->t.as<double>(), r, 1.0 / P->lambda, z, part, st, CLK_GEMV_N);
+    return;
+  }
+  // the same L t pass, finished together with the partials of r^T z
+  const int nb = cdiv(k, LN_COLS);
+  const int gx = cdiv(n, ln_rows<TA>());
+  const int64_t stride = (int64_t)gx * ln_rows<TA>();
+  clk_begin(CLK_GEMV_N, st);
+  k_ln_part<TA><<<dim3(gx, nb), 256, 0, st>>>(L, n, P->ld, k, P->t.as<double>(), part, stride);
+  LAUNCHCHK();
+  clk_end(CLK_GEMV_N, st);
+  const int np = fused_parts(n);
+  k_finish_n_dot<<<np, 256, 0, st>>>(part, nb, stride, n, r, 1.0 / P->lambda, z, rz_part);
+  LAUNCHCHK();
+  sum_parts64(rz_part, np, rz, st);
 }
 
 int64_t precond_work_doubles(int64_t n, int64_t ld, int64_t keff, int store) {
   (void)n;
-  const int64_t ldf = pad64(std::max<int64_t>(keff, 1));
-  int64_t w = gemv_work<double, true>(ldf, ldf);
-  if (store == FFK_FP64) w = std::max(w, gemv_work<double, false>(ld, keff));
-  else if (store == FFK_FP32) w = std::max(w, gemv_work<float, false>(ld, keff));
-  else w = std::max(w, gemv_work<bf16_t, false>(ld, keff));
-  return w;
+  if (store == FFK_FP64) return gemv_work<double>(ld, keff);
+  if (store == FFK_FP32) return gemv_work<float>(ld, keff);
+  return gemv_work<bf16_t>(ld, keff);
 }
 
 __global__ void k_scale(const double* r, double a, int64_t n, double* z) {
@@ -637,6 +731,20 @@ void precond_apply(const ffk_precond* P, const double* r, double* z, hipStream_t
   if (P->store == FFK_FP64) apply_t<double>(P, r, z, st);
   else if (P->store == FFK_FP32) apply_t<float>(P, r, z, st);
   else apply_t<bf16_t>(P, r, z, st);
+}
+
+void precond_apply_dot(const ffk_precond* P, const double* r, double* z, double* part, double* rz_dev,
+                       hipStream_t st) {
+  if (P->k_eff == 0) {
+    const int np = fused_parts(P->n);
+    k_scale_dot<<<np, 256, 0, st>>>(r, 1.0 / P->lambda, P->n, z, part);
+    LAUNCHCHK();
+    sum_parts64(part, np, rz_dev, st);
+    return;
+  }
+  if (P->store == FFK_FP64) apply_t<double>(P, r, z, st, part, rz_dev);
+  else if (P->store == FFK_FP32) apply_t<float>(P, r, z, st, part, rz_dev);
+  else apply_t<bf16_t>(P, r, z, st, part, rz_dev);
 }
 
 // L (n x k_eff) as a dense column-major FP64 matrix with leading dimension n.

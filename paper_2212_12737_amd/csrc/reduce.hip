@@ -54,6 +54,18 @@ void dot64(const double* a, const double* b, int64_t n, double* part, double* ou
   LAUNCHCHK();
 }
 
+int fused_parts(int64_t n) {
+  int64_t b = (n + 511) / 512;
+  if (b < 1) b = 1;
+  if (b > kRedParts) b = kRedParts;
+  return (int)b;
+}
+
+void sum_parts64(const double* part, int np, double* out, hipStream_t st) {
+  k_red_final<0><<<1, 256, 0, st>>>(part, np, out);
+  LAUNCHCHK();
+}
+
 void reduce_max64(const double* a, int64_t n, double* part, double* out, hipStream_t st) {
   const int np = nparts(n);
   k_red_part<1><<<np, 256, 0, st>>>(a, nullptr, n, part);
