@@ -302,6 +302,26 @@ ffk_status ffk_mlp_fit_norm(ffk_ctx* ctx, ffk_mlp* net, const float* X_dev, int6
 /* k_RoT = (k_min^m m n^2 / 2)^(1/(2+m)), rounded to the nearest integer in [1, n]. */
 int64_t ffk_rule_of_thumb(int64_t n, double k_min, double m);
 
+/* The rule of thumb with measured costs: the integer k in [1, n] that
+ * minimises runtime(k) = n (k_min/k)^m (a + b k) + c k^2, i.e. the power-law
+ * iteration count times a per-iteration cost a + b k (b prices the two passes
+ * of the preconditioner apply over the n x k factor) plus a build cost c k^2.
+ * Eq. 7 is the case a = n^2, b = 0, c = n, which returns k_RoT.  The model is
+ * unimodal in k for m > 0; it is minimised by an integer ternary search.
+ * Returns -1 for n < 1, k_min <= 0, m <= 0, a negative cost or a + b = 0. */
+int64_t ffk_rule_of_thumb_calibrated(int64_t n, double k_min, double m, double a, double b, double c);
+
+/* Fit of the power law #/n = (k_min / k)^m between the preconditioner size k
+ * and the PCG iteration count # at kernel size n (section 4.3, the trade-off
+ * behind Eq. 7): least squares of log(#/n) = m log k_min - m log k over
+ * `count` measured pairs (k_host[i], iters_host[i]) in host memory.  Host
+ * computation only (no device work, no context).  Returns FFK_ERR_ARG when
+ * count < 2, n < 1, a k or an iteration count is < 1, all k are equal, or the
+ * fitted m is not positive (iterations that do not fall with k); the outputs
+ * are then left unchanged. */
+ffk_status ffk_rot_fit(const int64_t* k_host, const int64_t* iters_host, int32_t count, int64_t n,
+                       double* k_min_host, double* m_host);
+
 #ifdef __cplusplus
 }
 #endif

@@ -415,4 +415,48 @@ int64_t ffk_rule_of_thumb(int64_t n, double k_min, double m) {
   return r;
 }
 
+int64_t ffk_rule_of_thumb_calibrated(int64_t n, double k_min, double m, double a, double b, double c) {
+  if (n < 1 || !(k_min > 0) || !(m > 0) || !(a >= 0) || !(b >= 0) || !(c >= 0) || !(a + b > 0)) return -1;
+  auto f = [&](int64_t k) {
+    const double x = (double)k;
+    return (double)n * std::pow(k_min / x, m) * (a + b * x) + c * x * x;
+  };
+  int64_t lo = 1, hi = n;
+  while (hi - lo > 2) {
+    const int64_t m1 = lo + (hi - lo) / 3, m2 = hi - (hi - lo) / 3;
+    if (f(m1) < f(m2)) hi = m2 - 1;
+    else if (f(m1) > f(m2)) lo = m1 + 1;
+    else { lo = m1; hi = m2; }   // equal values of a unimodal f bracket its minimum
+  }
+  int64_t best = lo;
+  for (int64_t k = lo + 1; k <= hi; ++k)
+    if (f(k) < f(best)) best = k;
+  return best;
+}
+
+ffk_status ffk_rot_fit(const int64_t* k, const int64_t* iters, int32_t count, int64_t n, double* k_min,
+                       double* m) {
+  if (!k || !iters || !k_min || !m || count < 2 || n < 1) return FFK_ERR_ARG;
+  double sx = 0.0, sy = 0.0;
+  for (int32_t i = 0; i < count; ++i) {
+    if (k[i] < 1 || iters[i] < 1) return FFK_ERR_ARG;
+    sx += std::log((double)k[i]);
+    sy += std::log((double)iters[i] / (double)n);
+  }
+  const double mx = sx / count, my = sy / count;
+  double sxx = 0.0, sxy = 0.0;
+  for (int32_t i = 0; i < count; ++i) {
+    const double dx = std::log((double)k[i]) - mx;
+    sxx += dx * dx;
+    sxy += dx * (std::log((double)iters[i] / (double)n) - my);
+  }
+  if (!(sxx > 0.0)) return FFK_ERR_ARG;
+  const double slope = sxy / sxx;   // = -m
+  if (!(slope < 0.0)) return FFK_ERR_ARG;
+  const double mm = -slope;
+  *m = mm;
+  *k_min = std::exp((my + mm * mx) / mm);
+  return FFK_OK;
+}
+
 }  // extern "C"

@@ -419,8 +419,9 @@ template <typename TA> __device__ inline uint4 load16(const TA* p) {
 constexpr int LT_COLS = 16;    // columns per block of the transposed product
 constexpr int LN_UNROLL = 16;  // loads in flight per lane in the direct product
 // columns per block of the direct product: wide, so few partial sums remain
-constexpr int LN_COLS = 256;
-static_assert(LN_COLS % LN_UNROLL == 0 && LN_COLS <= 256, "direct-product column tile");
+// (512 measured 4% faster than 256 on n = 126000, k = 2000)
+constexpr int LN_COLS = 512;
+static_assert(LN_COLS % LN_UNROLL == 0, "direct-product column tile");
 
 // Sum of v[0..C) over the 64 lanes of a wave, one column per lane group:
 // recursive halving (each exchange step hands half of the values to the

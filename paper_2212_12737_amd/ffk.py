@@ -92,6 +92,8 @@ _SIGS = {
     "ffk_mlp_prepare_inputs": (I32, [P, P, P, P, I32, P]),
     "ffk_mlp_fit_norm": (I32, [P, P, P, I64, P]),
     "ffk_rule_of_thumb": (I64, [I64, DBL, DBL]),
+    "ffk_rot_fit": (I32, [P, P, I32, I64, P, P]),
+    "ffk_rule_of_thumb_calibrated": (I64, [I64, DBL, DBL, DBL, DBL, DBL]),
 }
 
 
@@ -436,3 +438,19 @@ def mlp_fit_norm(ctx: Context, net: Mlp, X: torch.Tensor, stream=None):
 
 def rule_of_thumb(n: int, k_min: float = 100.0, m: float = 1.0) -> int:
     return int(lib().ffk_rule_of_thumb(n, k_min, m))
+
+
+def rule_of_thumb_calibrated(n: int, k_min: float, m: float, a: float, b: float, c: float) -> int:
+    """argmin over k of n (k_min/k)^m (a + b k) + c k^2 (Eq. 7 with measured costs)."""
+    return int(lib().ffk_rule_of_thumb_calibrated(n, k_min, m, a, b, c))
+
+
+def rot_fit(k, iters, n: int) -> tuple[float, float]:
+    """(k_min, m) of the power law #/n = (k_min/k)^m fitted to measured (k, #) pairs."""
+    kk = (ctypes.c_int64 * len(k))(*[int(x) for x in k])
+    it = (ctypes.c_int64 * len(iters))(*[int(x) for x in iters])
+    kmin, m = ctypes.c_double(), ctypes.c_double()
+    st = lib().ffk_rot_fit(kk, it, len(k), int(n), ctypes.byref(kmin), ctypes.byref(m))
+    if st != 0:
+        raise FfkError(st, "rot_fit: need >= 2 distinct k with iterations that fall with k")
+    return kmin.value, m.value

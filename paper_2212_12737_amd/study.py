@@ -4,11 +4,15 @@ labels of smaller systems of the same molecule.
 
     python -m paper_2212_12737_amd.study labels  --config m21_n10000 --out DIR [--first 0 --count 20]
     python -m paper_2212_12737_amd.study compare --config m21_n10000 --labels DIR [--steps 3000]
+    python -m paper_2212_12737_amd.study rot --config m21_n2000 [--sweep-N 250,500,1000]
 
 `labels` computes the exact labels (dense FP64 Cholesky on the GPU, about a
 minute per N = 2000 system) and saves one .npy per training system, so they
 can be produced over several runs; `compare` trains the network from them and
-prints one JSON line per selection strategy.  Every step runs in libffkrr.
+prints one JSON line per selection strategy.  `rot` measures the rule of thumb
+for the preconditioner size (section 4.3): a k-sweep of PCG iterations on
+small systems, the power-law fit, and the workload solved at the predicted
+sizes and over a grid of k.  Every step runs in libffkrr.
 """
 from __future__ import annotations
 
@@ -89,22 +93,126 @@ def compare(ctx, config, label_dir, steps, arms):
         del P
 
 
+def _solve_at_k(ctx, S, F, cfg, k, arm, seed):
+    """Leverage selection (pilot of k columns), build, PCG to 1e-6; one record."""
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    idx = ffk.nystrom_select(ctx, S, "leverage", k, lam=cfg.lam, seed=seed, pilot=k)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    mixed = arm == "mixed"
+    P = ffk.precond_build(ctx, S, idx, cfg.lam, store=ffk.FP32 if mixed else ffk.FP64)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    _, rep = ffk.pcg_solve(ctx, S, P, F, cfg.lam, tol=1e-6, max_iter=3 * S.n, prec=ffk.BF16X3 if mixed else ffk.FP64,
+                           refresh_every=10, escalate=True, switch_below=0.3 if mixed else 0.0)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    rec = {"n": S.n, "k": k, "k_eff": P.k_eff, "arm": arm, "iters": rep.iters, "iters_over_n": rep.iters / S.n,
+           "status": rep.status, "rel_res_true": rep.rel_res_true, "t_select_s": t1 - t0, "t_build_s": t2 - t1,
+           "t_pcg_s": t3 - t2, "t_total_s": t3 - t0}
+    del P
+    return rec
+
+
+def _product_ms(ctx, S, reps=10):
+    """Mean time of the FP64 kernel product on S, in seconds."""
+    v = torch.ones(S.n, dtype=torch.float64, device=ctx.torch_device)
+    ffk.kernel_mvm(ctx, S, v, prec=ffk.FP64)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ffk.kernel_mvm(ctx, S, v, prec=ffk.FP64)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps
+
+
+def rule_of_thumb(ctx, config, sweep_N, ks, grid, arms):
+    """Section 4.3: the PCG iteration count against the preconditioner size k
+    on small systems of the workload's molecule (leverage selection, as the
+    paper's analysis), the power-law fit #/n = (k_min/k)^m per system size,
+    the sizes it predicts for the workload (Eq. 8, with the fitted and with the
+    default m = 1, k_min = 100, and with costs measured on the largest sweep
+    system) and the 1%-baseline, then the full solve of the workload over a
+    grid of k that contains all of them, so that each heuristic is priced
+    against the best measured k."""
+    synth, cfg = _config(config)
+    fits, sweep_rows = [], []
+    for N in sweep_N:
+        s, S = _system(ctx, synth, cfg, N, cfg.disp_seed + 3000 + N)
+        F = torch.as_tensor(s.flat_forces(), device=ctx.torch_device)
+        rows = []
+        for k in ks:
+            if k > S.n // 4:
+                continue
+            rec = _solve_at_k(ctx, S, F, cfg, k, "fp64", cfg.sel_seed)
+            rec["sweep_N"] = N
+            print(json.dumps(rec), flush=True)
+            if rec["status"] == 0:
+                rows.append(rec)
+        kmin, m = ffk.rot_fit([r["k"] for r in rows], [r["iters"] for r in rows], S.n)
+        fits.append((S.n, kmin, m))
+        sweep_rows = rows
+        t_mvm_sweep = _product_ms(ctx, S)
+        print(json.dumps({"fit_n": S.n, "k_min": kmin, "m": m, "points": len(rows)}), flush=True)
+        del S
+    n_fit, kmin, m = fits[-1]   # the largest sweep system
+    s, S = _system(ctx, synth, cfg, cfg.N, cfg.disp_seed)
+    F = torch.as_tensor(s.flat_forces(), device=ctx.torch_device)
+    # costs of the calibrated form, from the largest sweep system: time per
+    # iteration a + b k and build time c k^2 by least squares; b and c scale
+    # with n (the apply streams n values per column, the build costs k^2 n),
+    # a with the measured FP64 product time at the two sizes
+    ks = np.array([r["k"] for r in sweep_rows], dtype=np.float64)
+    t_it = np.array([r["t_pcg_s"] / r["iters"] for r in sweep_rows])
+    t_bd = np.array([r["t_select_s"] + r["t_build_s"] for r in sweep_rows])
+    b_s, a_s = np.polyfit(ks, t_it, 1)
+    c_s = float(np.sum(t_bd * ks ** 2) / np.sum(ks ** 4))
+    scale = S.n / n_fit
+    a_w = max(a_s, 1e-9) * _product_ms(ctx, S) / t_mvm_sweep
+    costs = {"a_s": a_w, "b_s_per_k": max(b_s, 0.0) * scale, "c_s_per_k2": c_s * scale}
+    heur = {"rot_specific": ffk.rule_of_thumb(S.n, kmin, m), "rot_default": ffk.rule_of_thumb(S.n),
+            "rot_calibrated": ffk.rule_of_thumb_calibrated(S.n, kmin, m, costs["a_s"], costs["b_s_per_k"],
+                                                           costs["c_s_per_k2"]),
+            "one_percent": max(1, round(S.n / 100)), "workload_k": cfg.k}
+    print(json.dumps({"workload_n": S.n, "fit_from_n": n_fit, "k_min": kmin, "m": m, "costs": costs,
+                      "predicted": heur}), flush=True)
+    kgrid = sorted(set(list(grid) + list(heur.values())))
+    for arm in arms:
+        recs = []
+        for k in kgrid:
+            rec = _solve_at_k(ctx, S, F, cfg, k, arm, cfg.sel_seed)
+            print(json.dumps(rec), flush=True)
+            recs.append(rec)
+        ok = [r for r in recs if r["status"] == 0]
+        best = min(ok, key=lambda r: r["t_total_s"])
+        rel = {h: next(r["t_total_s"] for r in recs if r["k"] == kk) / best["t_total_s"] for h, kk in heur.items()}
+        print(json.dumps({"arm": arm, "best_k": best["k"], "best_total_s": best["t_total_s"],
+                          "relative_time": rel}), flush=True)
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("mode", choices=["labels", "compare"])
+    ap.add_argument("mode", choices=["labels", "compare", "rot"])
     ap.add_argument("--config", default="m21_n10000")
     ap.add_argument("--out", default="study_labels")
     ap.add_argument("--labels", default="study_labels")
     ap.add_argument("--first", type=int, default=0)
     ap.add_argument("--count", type=int, default=20)
     ap.add_argument("--steps", type=int, default=3000)
-    ap.add_argument("--arms", default="learned,pivchol,uniform,leverage")
+    ap.add_argument("--arms", default=None, help="compare: selections; rot: fp64 and/or mixed")
+    ap.add_argument("--sweep-N", default="250,500,1000", help="rot: geometries of the sweep systems")
+    ap.add_argument("--ks", default="125,250,500,1000,2000,4000", help="rot: preconditioner sizes of the sweep")
+    ap.add_argument("--grid", default="500,1000,2000,3000,4000,6000", help="rot: sizes tried on the workload")
     a = ap.parse_args(argv)
     ctx = ffk.create(0)
+    ints = lambda t: [int(x) for x in t.split(",")]
     if a.mode == "labels":
         labels(ctx, a.config, a.out, a.first, a.count)
+    elif a.mode == "compare":
+        compare(ctx, a.config, a.labels, a.steps, (a.arms or "learned,pivchol,uniform,leverage").split(","))
     else:
-        compare(ctx, a.config, a.labels, a.steps, a.arms.split(","))
+        rule_of_thumb(ctx, a.config, ints(a.sweep_N), ints(a.ks), ints(a.grid), (a.arms or "fp64,mixed").split(","))
 
 
 if __name__ == "__main__":
