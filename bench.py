@@ -250,7 +250,8 @@ def main(argv=None) -> int:
     ap.add_argument("--steps", type=int, default=3, help="timed solves")
     ap.add_argument("--warmup", type=int, default=1, help="untimed solves before the timed ones")
     ap.add_argument("--config", default="m21_n2000")
-    ap.add_argument("--mvm-configs", default="m60_n20000", help="comma list of further systems for kernel-product rates")
+    ap.add_argument("--mvm-configs", default="m9_n200,m42_n5000,m21_n10000,m60_n20000",
+                    help="comma list of further systems for kernel-product rates")
     ap.add_argument("--mvm-steps", type=int, default=20)
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison solve")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle sample")

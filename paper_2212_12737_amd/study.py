@@ -5,6 +5,7 @@ labels of smaller systems of the same molecule.
     python -m paper_2212_12737_amd.study labels  --config m21_n10000 --out DIR [--first 0 --count 20]
     python -m paper_2212_12737_amd.study compare --config m21_n10000 --labels DIR [--steps 3000]
     python -m paper_2212_12737_amd.study rot --config m21_n2000 [--sweep-N 250,500,1000]
+    python -m paper_2212_12737_amd.study spectrum --config m21_n2000 [--spec-N 100 --spec-ks 100,400,1600]
 
 `labels` computes the exact labels (dense FP64 Cholesky on the GPU, about a
 minute per N = 2000 system) and saves one .npy per training system, so they
@@ -12,7 +13,10 @@ can be produced over several runs; `compare` trains the network from them and
 prints one JSON line per selection strategy.  `rot` measures the rule of thumb
 for the preconditioner size (section 4.3): a k-sweep of PCG iterations on
 small systems, the power-law fit, and the workload solved at the predicted
-sizes and over a grid of k.  Every step runs in libffkrr.
+sizes and over a grid of k.  `spectrum` compares the spectrum of the
+preconditioned matrix across strategies and sizes with the optimal rank-k
+preconditioner (section 4.1), on a small system.  Every step of the solver
+runs in libffkrr; the dense eigen-analysis of `spectrum` runs on the host.
 """
 from __future__ import annotations
 
@@ -191,9 +195,67 @@ def rule_of_thumb(ctx, config, sweep_N, ks, grid, arms):
                           "relative_time": rel}), flush=True)
 
 
+def svd_preconditioned_spectrum(eigs, lam, k):
+    """Eigenvalues, descending, of P^-1 K_lambda for the optimal rank-k
+    preconditioner P = U_k diag(e_1..e_k) U_k^T + lam I built from the k
+    dominant eigenpairs of K (section 2.2): the k dominant directions map to
+    (e_i + lam)/(e_i + lam) = 1, every other one to (e_i + lam)/lam."""
+    e = np.sort(np.asarray(eigs, dtype=np.float64))[::-1]
+    k = min(int(k), e.size)
+    return np.sort(np.concatenate([np.ones(k), (e[k:] + lam) / lam]))[::-1]
+
+
+def nystrom_preconditioned_spectrum(K, L, lam):
+    """Eigenvalues, descending, of P^-1 K_lambda with P = L L^T + lam I (Eq. 3),
+    from the symmetric-definite pencil (K + lam I, P)."""
+    import scipy.linalg as sla
+    n = K.shape[0]
+    Kl = K + lam * np.eye(n)
+    P = L @ L.T + lam * np.eye(n)
+    return sla.eigh(Kl, P, eigvals_only=True)[::-1]
+
+
+def spectrum(ctx, config, N, ks, strategies, top):
+    """Section 4.1: the spectrum of P^-1 K_lambda for several preconditioner
+    sizes k and selection strategies on a small system of the workload's
+    molecule, against the optimal rank-k (eigendecomposition, "SVD")
+    preconditioner, with the FP64 PCG iteration count of each.  K comes from
+    the library's column kernel, L from the library's factor; the dense
+    eigen-analysis runs on the host (double precision LAPACK), which limits
+    this study to small n."""
+    synth, cfg = _config(config)
+    s, S = _system(ctx, synth, cfg, N, cfg.disp_seed + 5000 + N)
+    n, lam = S.n, cfg.lam
+    F = torch.as_tensor(s.flat_forces(), device=ctx.torch_device)
+    K = ffk.kernel_columns(ctx, S, torch.arange(n)).cpu().numpy()
+    K = 0.5 * (K + K.T)
+    eigs = np.linalg.eigvalsh(K)[::-1]
+    print(json.dumps({"n": n, "lambda": lam, "kappa_K_lambda": float((eigs[0] + lam) / (max(eigs[-1], 0.0) + lam)),
+                      "eig_top": [float(eigs[i]) for i in (0, 9, 99, min(999, n - 1))]}), flush=True)
+    out = {"eigs_K": eigs[:top]}
+    for k in ks:
+        sv = svd_preconditioned_spectrum(eigs, lam, k)
+        row = {"k": k, "strategy": "svd", "kappa": float(sv[0] / sv[-1]), "top": [float(sv[i]) for i in (0, 9, 49, top - 1)]}
+        print(json.dumps(row), flush=True)
+        out["svd_%d" % k] = sv[:top]
+        for strat in strategies:
+            idx = ffk.nystrom_select(ctx, S, strat, k, lam=lam, seed=cfg.sel_seed, pilot=k if strat == "leverage" else 0)
+            P = ffk.precond_build(ctx, S, idx, lam, store=ffk.FP64)
+            L = ffk.precond_export(ctx, P, n).cpu().numpy()
+            _, rep = ffk.pcg_solve(ctx, S, P, F, lam, tol=1e-6, max_iter=4 * n, prec=ffk.FP64)
+            w = nystrom_preconditioned_spectrum(K, L, lam)
+            row = {"k": k, "strategy": strat, "k_eff": P.k_eff, "kappa": float(w[0] / w[-1]),
+                   "kappa_over_svd": float((w[0] / w[-1]) / (sv[0] / sv[-1])),
+                   "top": [float(w[i]) for i in (0, 9, 49, top - 1)], "pcg_iters": rep.iters, "status": rep.status}
+            print(json.dumps(row), flush=True)
+            out["%s_%d" % (strat, k)] = w[:top]
+            del P
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("mode", choices=["labels", "compare", "rot"])
+    ap.add_argument("mode", choices=["labels", "compare", "rot", "spectrum"])
     ap.add_argument("--config", default="m21_n10000")
     ap.add_argument("--out", default="study_labels")
     ap.add_argument("--labels", default="study_labels")
@@ -204,6 +266,9 @@ def main(argv=None):
     ap.add_argument("--sweep-N", default="250,500,1000", help="rot: geometries of the sweep systems")
     ap.add_argument("--ks", default="125,250,500,1000,2000,4000", help="rot: preconditioner sizes of the sweep")
     ap.add_argument("--grid", default="500,1000,2000,3000,4000,6000", help="rot: sizes tried on the workload")
+    ap.add_argument("--spec-N", type=int, default=100, help="spectrum: geometries of the system")
+    ap.add_argument("--spec-ks", default="100,400,1600", help="spectrum: preconditioner sizes")
+    ap.add_argument("--spec-out", default=None, help="spectrum: .npz with the dominant eigenvalues")
     a = ap.parse_args(argv)
     ctx = ffk.create(0)
     ints = lambda t: [int(x) for x in t.split(",")]
@@ -211,8 +276,12 @@ def main(argv=None):
         labels(ctx, a.config, a.out, a.first, a.count)
     elif a.mode == "compare":
         compare(ctx, a.config, a.labels, a.steps, (a.arms or "learned,pivchol,uniform,leverage").split(","))
-    else:
+    elif a.mode == "rot":
         rule_of_thumb(ctx, a.config, ints(a.sweep_N), ints(a.ks), ints(a.grid), (a.arms or "fp64,mixed").split(","))
+    else:
+        out = spectrum(ctx, a.config, a.spec_N, ints(a.spec_ks), (a.arms or "uniform,leverage,pivchol").split(","), 150)
+        if a.spec_out:
+            np.savez(a.spec_out, **out)
 
 
 if __name__ == "__main__":
