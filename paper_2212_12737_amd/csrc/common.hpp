@@ -257,6 +257,8 @@ void trtri_lower(double* A, int64_t n, int64_t lda, hipStream_t st);
 // reduce.hip -- deterministic two-stage reductions; `part` holds >= kRedParts doubles.
 constexpr int kRedParts = 1024;
 void dot64(const double* a, const double* b, int64_t n, double* part, double* out_dev, hipStream_t st);
+// The first stage of dot64 alone: block partials into part; returns their count.
+int dot64_parts(const double* a, const double* b, int64_t n, double* part, hipStream_t st);
 void reduce_max64(const double* a, int64_t n, double* part, double* out_dev, hipStream_t st);
 // Kernels that fuse a dot product into an elementwise pass run fused_parts(n)
 // blocks of 256 lanes over a grid-stride loop, reduce each block with
@@ -271,6 +273,14 @@ __device__ inline double block_sum256(double v, double* sh /* 256 doubles of LDS
     __syncthreads();
   }
   return sh[0];
+}
+// Fixed-order total of part[0..np) by one block of 256 lanes, returned to
+// every lane: the order of the second stage of dot64, so a kernel that needs
+// the total can form it itself instead of waiting for a separate launch.
+__device__ inline double sum_parts_block(const double* part, int np, double* sh) {
+  double acc = 0.0;
+  for (int e = threadIdx.x; e < np; e += 256) acc += part[e];
+  return block_sum256(acc, sh);
 }
 
 // select.hip
@@ -293,9 +303,10 @@ int64_t icd_forced(ffk_system* sys, const int64_t* idx, int64_t k, double shift,
 ffk_precond* precond_build(ffk_system* sys, const int64_t* idx, int64_t k, double lambda,
                            int store, bool lowmem, bool* dropped, hipStream_t st);
 void precond_apply(const ffk_precond* P, const double* r, double* z, hipStream_t st);
-// z = M^-1 r and *rz_dev = r^T z (part: kRedParts doubles of workspace)
-void precond_apply_dot(const ffk_precond* P, const double* r, double* z, double* part, double* rz_dev,
-                       hipStream_t st);
+// z = M^-1 r and the block partials of r^T z in part (kRedParts doubles);
+// returns the number of partials (fixed order; sum them with sum_parts64 or
+// sum_parts_block)
+int precond_apply_parts(const ffk_precond* P, const double* r, double* z, double* part, hipStream_t st);
 
 // pcg.hip
 ffk_status pcg_solve(ffk_system* sys, const ffk_precond* P, const double* F, double* alpha,

@@ -28,13 +28,18 @@ namespace ffk {
 enum { S_RHO0 = 0, S_RHO1 = 1, S_PAP = 2, S_RR = 3, S_ZQ = 4, S_FF = 5, S_TMP = 6, NSC = 8 };
 
 // x += g p, r -= g q with g = rho / p^T q, and the block partials of |r|^2 of
-// the updated r (fused_parts grid)
+// the updated r (fused_parts grid).  Every block forms p^T q itself from the
+// np_pq partials of dot64_parts (same fixed order in every block); block 0
+// stores it in sc.
 __global__ __launch_bounds__(256) void k_axpy2_rr(double* __restrict__ x, double* __restrict__ r,
                                                   const double* __restrict__ p, const double* __restrict__ q,
-                                                  const double* __restrict__ sc, int rho, int64_t n,
+                                                  double* __restrict__ sc, int rho, int64_t n,
+                                                  const double* __restrict__ pq_part, int np_pq,
                                                   double* __restrict__ rr_part) {
-  __shared__ double sh[256];
-  const double g = sc[rho] / sc[S_PAP];
+  __shared__ double sh[256], sh_pq[256];
+  const double pq = sum_parts_block(pq_part, np_pq, sh_pq);
+  if (blockIdx.x == 0 && threadIdx.x == 0) sc[S_PAP] = pq;
+  const double g = sc[rho] / pq;
   double acc = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
     x[i] += g * p[i];
@@ -46,9 +51,21 @@ __global__ __launch_bounds__(256) void k_axpy2_rr(double* __restrict__ x, double
   if (threadIdx.x == 0) rr_part[blockIdx.x] = s;
 }
 
-// pn = z + beta p (out of place, so that a speculative update can be redone)
-__global__ void k_update_p(double* __restrict__ pn, const double* __restrict__ p, const double* __restrict__ z,
-                           const double* __restrict__ sc, int rho_old, int rho_new, int flexible, int64_t n) {
+// pn = z + beta p (out of place, so that a speculative update can be redone).
+// With rz_part, every block forms rho_new = r^T z from the np_rz partials of
+// the preconditioner apply (fixed order) and block 0 stores it in sc.
+__global__ __launch_bounds__(256) void k_update_p(double* __restrict__ pn, const double* __restrict__ p,
+                                                  const double* __restrict__ z, double* __restrict__ sc, int rho_old,
+                                                  int rho_new, int flexible, int64_t n,
+                                                  const double* __restrict__ rz_part, int np_rz) {
+  __shared__ double sh[256];
+  double rn;
+  if (rz_part) {
+    rn = sum_parts_block(rz_part, np_rz, sh);
+    if (blockIdx.x == 0 && threadIdx.x == 0) sc[rho_new] = rn;
+  } else {
+    rn = sc[rho_new];
+  }
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   double beta;
@@ -56,7 +73,7 @@ __global__ void k_update_p(double* __restrict__ pn, const double* __restrict__ p
     const double g = sc[rho_old] / sc[S_PAP];
     beta = -g * sc[S_ZQ] / sc[rho_old];
   } else {
-    beta = sc[rho_new] / sc[rho_old];
+    beta = rn / sc[rho_old];
   }
   pn[i] = z[i] + beta * p[i];
 }
@@ -112,14 +129,15 @@ ffk_status pcg_solve(ffk_system* s, const ffk_precond* P, const double* F, doubl
   const bool timing = o->timing != 0;
   double t_mvm = 0, t_prec = 0, t_vec = 0, t_ref = 0;
 
-  DBuf r(n * 8), z(n * 8), p(n * 8), p2(n * 8), q(n * 8), tmp(n * 8), best(n * 8), sc(NSC * 8), part(kRedParts * 8);
+  DBuf r(n * 8), z(n * 8), p(n * 8), p2(n * 8), q(n * 8), tmp(n * 8), best(n * 8), sc(NSC * 8), part(2 * kRedParts * 8);
   double* R = r.as<double>();
   double* Z = z.as<double>();
   double* Pv = p.as<double>();
   double* Pn = p2.as<double>();
   double* Q = q.as<double>();
   double* SC = sc.as<double>();
-  double* PART = part.as<double>();
+  double* PART = part.as<double>();              // partials of one reduction
+  double* PART2 = PART + kRedParts;                // a second set, for |r|^2 beside p^T q
   const int nb = cdiv(n, 256);
   const int np_fused = fused_parts(n);
   s->ctx->host_scratch.ensure(64);
@@ -191,16 +209,21 @@ ffk_status pcg_solve(ffk_system* s, const ffk_precond* P, const double* F, doubl
   };
   // Next direction from the current r: z = M^-1 r, rho_new = r^T z, pn = z + beta p.
   auto next_direction = [&](int rho_new) {
+    int np_rz = 0;   // > 0: r^T z is still in PART as partials, summed by k_update_p
     if (P) {
       Timer tm(timing, st, &t_prec);
-      precond_apply_dot(P, R, Z, PART, SC + rho_new, st);
+      np_rz = precond_apply_parts(P, R, Z, PART, st);
     } else {
       apply_prec(R, Z);
       dot64(R, Z, n, PART, SC + rho_new, st);
     }
     Timer tm(timing, st, &t_vec);
-    if (o->flexible) dot64(Z, Q, n, PART, SC + S_ZQ, st);
-    k_update_p<<<nb, 256, 0, st>>>(Pn, Pv, Z, SC, rho, rho_new, o->flexible, n);
+    if (o->flexible) {
+      if (np_rz) sum_parts64(PART, np_rz, SC + rho_new, st);
+      np_rz = 0;
+      dot64(Z, Q, n, PART, SC + S_ZQ, st);
+    }
+    k_update_p<<<nb, 256, 0, st>>>(Pn, Pv, Z, SC, rho, rho_new, o->flexible, n, np_rz ? PART : nullptr, np_rz);
     LAUNCHCHK();
   };
   // The host reads |r|^2 and p^T q once per iteration.  Except on refresh
@@ -216,10 +239,10 @@ ffk_status pcg_solve(ffk_system* s, const ffk_precond* P, const double* F, doubl
     }
     {
       Timer tm(timing, st, &t_vec);
-      dot64(Pv, Q, n, PART, SC + S_PAP, st);
-      k_axpy2_rr<<<np_fused, 256, 0, st>>>(alpha, R, Pv, Q, SC, rho, n, PART);
+      const int np_pq = dot64_parts(Pv, Q, n, PART, st);
+      k_axpy2_rr<<<np_fused, 256, 0, st>>>(alpha, R, Pv, Q, SC, rho, n, PART, np_pq, PART2);
       LAUNCHCHK();
-      sum_parts64(PART, np_fused, SC + S_RR, st);
+      sum_parts64(PART2, np_fused, SC + S_RR, st);
       HIPCHK(hipMemcpyAsync(hs, SC + S_PAP, 16, hipMemcpyDeviceToHost, st));
       HIPCHK(hipEventRecord(done.e, st));
     }

@@ -501,18 +501,18 @@ __global__ __launch_bounds__(256) void k_lt_part(const TA* __restrict__ A, int64
         (red[0][threadIdx.x] + red[1][threadIdx.x]) + (red[2][threadIdx.x] + red[3][threadIdx.x]);
 }
 
-// y[c] = sum_b part[b][c]
-__global__ void k_sum_rows(const double* __restrict__ part, int nb, int64_t ncol, double* __restrict__ y) {
-  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= ncol) return;
-  double a0 = 0.0, a1 = 0.0;
-  int b = 0;
-  for (; b + 2 <= nb; b += 2) {
-    a0 += part[(int64_t)b * ncol + c];
-    a1 += part[(int64_t)(b + 1) * ncol + c];
-  }
-  if (b < nb) a0 += part[(int64_t)b * ncol + c];
-  y[c] = a0 + a1;
+// y[c] = sum_b part[b][c]: 16 columns per block of 256 lanes; the 16 lanes of
+// column c take row blocks q, q + 16, ... and combine by a fixed butterfly
+__global__ __launch_bounds__(256) void k_sum_rows(const double* __restrict__ part, int nb, int64_t ncol,
+                                                  double* __restrict__ y) {
+  const int64_t c = (int64_t)blockIdx.x * 16 + (threadIdx.x >> 4);
+  const int q = threadIdx.x & 15;
+  double s = 0.0;
+  if (c < ncol)
+    for (int b = q; b < nb; b += 16) s += part[(int64_t)b * ncol + c];
+#pragma unroll
+  for (int off = 8; off >= 1; off >>= 1) s += __shfl_xor(s, off);
+  if (q == 0 && c < ncol) y[c] = s;
 }
 
 // part[blockIdx.y][i] = sum over the block's columns c of A[i + c lda] t[c].
@@ -629,7 +629,7 @@ static void gemv_t(const TA* A, int64_t nrow, int64_t lda, int64_t ncol, const d
   k_lt_part<TA, LT_COLS, LT_RR><<<dim3(cdiv(ncol, LT_COLS), nb), 256, 0, st>>>(A, nrow, lda, ncol, x, part);
   LAUNCHCHK();
   if (clk >= 0) clk_end(clk, st);
-  k_sum_rows<<<cdiv(ncol, 256), 256, 0, st>>>(part, nb, ncol, y);
+  k_sum_rows<<<cdiv(ncol, 16), 256, 0, st>>>(part, nb, ncol, y);
   LAUNCHCHK();
 }
 
@@ -679,8 +679,7 @@ __global__ __launch_bounds__(256) void k_tri_dots(const double* __restrict__ A, 
 }
 
 template <typename TA>
-static void apply_t(const ffk_precond* P, const double* r, double* z, hipStream_t st, double* rz_part = nullptr,
-                    double* rz = nullptr) {
+static void apply_t(const ffk_precond* P, const double* r, double* z, hipStream_t st, double* rz_part = nullptr) {
   const TA* L = P->L.as<TA>();
   const int64_t n = P->n, k = P->k_eff;
   const double* F = P->Finv.as<double>();
@@ -693,7 +692,7 @@ static void apply_t(const ffk_precond* P, const double* r, double* z, hipStream_
   k_tri_dots<true><<<k, 256, 0, st>>>(F, P->ldf, k, P->t1.as<double>(), P->t.as<double>());
   LAUNCHCHK();
   clk_end(CLK_CORE, st);
-  if (!rz) {
+  if (!rz_part) {
     gemv_n<TA>(L, n, P->ld, k, P->t.as<double>(), r, 1.0 / P->lambda, z, part, st, CLK_GEMV_N);
     return;
   }
@@ -708,7 +707,6 @@ static void apply_t(const ffk_precond* P, const double* r, double* z, hipStream_
   const int np = fused_parts(n);
   k_finish_n_dot<<<np, 256, 0, st>>>(part, nb, stride, n, r, 1.0 / P->lambda, z, rz_part);
   LAUNCHCHK();
-  sum_parts64(rz_part, np, rz, st);
 }
 
 int64_t precond_work_doubles(int64_t n, int64_t ld, int64_t keff, int store) {
@@ -734,18 +732,19 @@ void precond_apply(const ffk_precond* P, const double* r, double* z, hipStream_t
   else apply_t<bf16_t>(P, r, z, st);
 }
 
-void precond_apply_dot(const ffk_precond* P, const double* r, double* z, double* part, double* rz_dev,
-                       hipStream_t st) {
+int precond_apply_parts(const ffk_precond* P, const double* r, double* z, double* part, hipStream_t st) {
+  const int np = fused_parts(P->n);
   if (P->k_eff == 0) {
-    const int np = fused_parts(P->n);
     k_scale_dot<<<np, 256, 0, st>>>(r, 1.0 / P->lambda, P->n, z, part);
     LAUNCHCHK();
-    sum_parts64(part, np, rz_dev, st);
-    return;
+  } else if (P->store == FFK_FP64) {
+    apply_t<double>(P, r, z, st, part);
+  } else if (P->store == FFK_FP32) {
+    apply_t<float>(P, r, z, st, part);
+  } else {
+    apply_t<bf16_t>(P, r, z, st, part);
   }
-  if (P->store == FFK_FP64) apply_t<double>(P, r, z, st, part, rz_dev);
-  else if (P->store == FFK_FP32) apply_t<float>(P, r, z, st, part, rz_dev);
-  else apply_t<bf16_t>(P, r, z, st, part, rz_dev);
+  return np;
 }
 
 // L (n x k_eff) as a dense column-major FP64 matrix with leading dimension n.

@@ -46,6 +46,13 @@ static int nparts(int64_t n) {
   return (int)b;
 }
 
+int dot64_parts(const double* a, const double* b, int64_t n, double* part, hipStream_t st) {
+  const int np = nparts(n);
+  k_red_part<0><<<np, 256, 0, st>>>(a, b, n, part);
+  LAUNCHCHK();
+  return np;
+}
+
 void dot64(const double* a, const double* b, int64_t n, double* part, double* out, hipStream_t st) {
   const int np = nparts(n);
   k_red_part<0><<<np, 256, 0, st>>>(a, b, n, part);
