@@ -399,6 +399,7 @@ struct SegD {
 struct DmaArgs {
   int nseg;
   SegD seg[2];
+  int lower_only;   // square tiles strictly above the diagonal do nothing (symmetric products)
 };
 
 // Tile shape of the pipelined engine: BM x BN block tile computed by WM x WN
@@ -431,6 +432,7 @@ __global__ __launch_bounds__(TL::NT) void gemm_dma_kernel(DmaArgs g, Epi epi) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   int tmi, tni;
   tile_coords(tmi, tni);
+  if (g.lower_only && tni > tmi) return;
   const int m0 = tmi * BM, n0 = tni * BN;
   const int wm = wave / WN, wn = wave % WN;
   const int t0 = g.seg[0].K / BK;

@@ -211,13 +211,21 @@ static int64_t icd_forced_f32(ffk_system* s, const int64_t* idx, int64_t k, floa
 }
 
 // ----------------------------------------------------------------- build ----
-__global__ void k_f64_to_f32(const double* a, float* b, int64_t n) {
+// The stored factor, and in L64 an FP64 copy of exactly the stored values,
+// so that the core can be formed from L64 on the FP64 MFMA engine.
+__global__ void k_round_f32(double* L64, float* L32, int64_t n) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e < n) b[e] = (float)a[e];
+  if (e >= n) return;
+  const float f = (float)L64[e];
+  L32[e] = f;
+  L64[e] = (double)f;
 }
-__global__ void k_f64_to_bf16(const double* a, bf16_t* b, int64_t n) {
+__global__ void k_round_bf16(double* L64, bf16_t* Lb, int64_t n) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e < n) b[e] = f2bf((float)a[e]);
+  if (e >= n) return;
+  const bf16_t h = f2bf((float)L64[e]);
+  Lb[e] = h;
+  L64[e] = (double)bf2f(h);
 }
 // zero the strict upper triangle of a column-major k x k matrix (ld rows)
 __global__ void k_zero_upper(double* A, int64_t k, int64_t ld) {
@@ -272,6 +280,48 @@ static void gram_cols(const TI* L, int64_t n, int64_t ld, int64_t k, double* C, 
   LAUNCHCHK();
 }
 
+// core[r + c ldc] = sum_z part[z][r][c] for r >= c (the lower triangle),
+// from the split-K partials of gram_dma (plane = k ldp doubles per split)
+__global__ void k_gram_reduce(const double* __restrict__ part, int splits, int64_t k, int64_t ldp, int64_t plane,
+                              double* __restrict__ C, int64_t ldc) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= k * k) return;
+  const int64_t r = e / k, c = e % k;
+  if (r < c) return;
+  double a = 0.0;
+  for (int z = 0; z < splits; ++z) a += part[(int64_t)z * plane + r * ldp + c];
+  C[r + c * ldc] = a;
+}
+
+// Rows of the Gram operand are padded to this (the tile of gram_dma).
+constexpr int64_t kGramTile = 128;
+
+// Lower triangle of core = L^T L from the FP64 factor on the pipelined FP64
+// MFMA engine.  The columns of the column-major L are the K-contiguous
+// operand rows (K = ld, zero padding rows), for A and B alike; L holds kp
+// columns (a multiple of the tile) so that every tile row is allocated.  Only
+// tiles on or below the diagonal run, split over K for enough workgroups,
+// and a fixed-order pass sums the splits.
+static void gram_dma(const double* L, int64_t ld, int64_t k, int64_t kp, double* C, int64_t ldc, hipStream_t st) {
+  typedef DmaTile<kGramTile, kGramTile, 2, 2, 4> TG;
+  require(kp % kGramTile == 0 && kp >= k && ld % 8 == 0, "gram_dma: operand padding");
+  const int64_t nt = kp / kGramTile;
+  const int64_t lower = nt * (nt + 1) / 2;
+  int splits = 1;
+  while (lower * splits < 512 && splits < 16 && ld / 8 >= (int64_t)splits * 2 * 64) splits *= 2;
+  DBuf part((size_t)splits * k * kp * 8);
+  DmaArgs g{};
+  g.nseg = 1;
+  g.lower_only = 1;
+  g.seg[0] = SegD{L, nullptr, L, nullptr, ld, ld, (int)ld};
+  EpiPart<double> e{part.as<double>(), kp, (int)k, (int)k};
+  gemm_dma_kernel<double, TG, false, EpiPart<double>><<<dim3((unsigned)nt, (unsigned)nt, splits), TG::NT, 0, st>>>(g, e);
+  LAUNCHCHK();
+  k_gram_reduce<<<cdiv(k * k, 256), 256, 0, st>>>(part.as<double>(), splits, k, kp, k * kp, C, ldc);
+  LAUNCHCHK();
+  HIPCHK(hipStreamSynchronize(st));   // before the partials are freed
+}
+
 int64_t precond_work_doubles(int64_t n, int64_t ld, int64_t keff, int store);
 
 // compact the kept columns to the front (in order; a column only moves left)
@@ -312,8 +362,10 @@ ffk_precond* precond_build(ffk_system* s, const int64_t* idx, int64_t k, double 
     keff = icd_forced_f32(s, idx, k, P->L.as<float>(), ld, &kept, st);
     compact_columns(P->L.as<char>(), ld, 4, kept, st);
   } else {
-    L64.alloc(ld * k * 8);
-    HIPCHK(hipMemsetAsync(L64.get(), 0, ld * k * 8, st));
+    // columns padded to the Gram tile; the extra ones stay zero
+    const int64_t kp = (k + kGramTile - 1) / kGramTile * kGramTile;
+    L64.alloc(ld * kp * 8);
+    HIPCHK(hipMemsetAsync(L64.get(), 0, ld * kp * 8, st));
     keff = icd_forced(s, idx, k, 0.0, L64.as<double>(), ld, &kept, st);
     compact_columns(L64.as<char>(), ld, 8, kept, st);
   }
@@ -326,23 +378,22 @@ ffk_precond* precond_build(ffk_system* s, const int64_t* idx, int64_t k, double 
   HIPCHK(hipMemsetAsync(core.get(), 0, ldf * ke * 8, st));
   if (lowmem) {
     if (keff > 0) gram_cols<float>(P->L.as<float>(), n, ld, keff, core.as<double>(), ldf, st);
-  } else if (store == FFK_FP64) {
-    if (keff > 0) gram_cols<double>(L64.as<double>(), n, ld, keff, core.as<double>(), ldf, st);
-    P->L = std::move(L64);
-  } else if (store == FFK_FP32) {
-    P->L.alloc(ld * ke * 4);
-    k_f64_to_f32<<<cdiv(ld * keff, 256), 256, 0, st>>>(L64.as<double>(), P->L.as<float>(), ld * keff);
-    LAUNCHCHK();
-    HIPCHK(hipStreamSynchronize(st));
-    L64.release();
-    if (keff > 0) gram_cols<float>(P->L.as<float>(), n, ld, keff, core.as<double>(), ldf, st);
   } else {
-    P->L.alloc(ld * ke * 2);
-    k_f64_to_bf16<<<cdiv(ld * keff, 256), 256, 0, st>>>(L64.as<double>(), P->L.as<bf16_t>(), ld * keff);
-    LAUNCHCHK();
-    HIPCHK(hipStreamSynchronize(st));
-    L64.release();
-    if (keff > 0) gram_cols<bf16_t>(P->L.as<bf16_t>(), n, ld, keff, core.as<double>(), ldf, st);
+    // the core is formed from the stored factor: FP64 as is, FP32 and BF16
+    // after rounding L64 to exactly the stored values
+    const int64_t kp = (k + kGramTile - 1) / kGramTile * kGramTile;
+    if (store == FFK_FP32) {
+      P->L.alloc(ld * ke * 4);
+      if (keff > 0) k_round_f32<<<cdiv(ld * keff, 256), 256, 0, st>>>(L64.as<double>(), P->L.as<float>(), ld * keff);
+      LAUNCHCHK();
+    } else if (store == FFK_BF16) {
+      P->L.alloc(ld * ke * 2);
+      if (keff > 0) k_round_bf16<<<cdiv(ld * keff, 256), 256, 0, st>>>(L64.as<double>(), P->L.as<bf16_t>(), ld * keff);
+      LAUNCHCHK();
+    }
+    if (keff > 0) gram_dma(L64.as<double>(), ld, keff, kp, core.as<double>(), ldf, st);
+    if (store == FFK_FP64) P->L = std::move(L64);
+    else L64.release();
   }
   if (keff > 0) {
     k_add_diag<<<cdiv(keff, 256), 256, 0, st>>>(core.as<double>(), keff, ldf, lambda);
