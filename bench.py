@@ -43,8 +43,6 @@ sys.path.insert(0, ROOT)
 PEAK_TFLOPS = {"bf16": 2500.0, "bf16x3": 2500.0, "fp32": 157.3, "fp64": 78.6}
 PEAK_HBM_GBS = 8000.0
 TOL = 1e-6
-SWITCH_BELOW = 0.3
-REFRESH = 10
 CLOCK_STRIDE = 16       # event pairs around every 16th launch of each clocked kernel
 
 
@@ -126,6 +124,7 @@ def solve(ffk, ctx, R, F, cfg, arm: str, net=None):
         torch.cuda.synchronize()
         t2 = time.perf_counter()
     prec = {"fp64": ffk.FP64, "mixed": ffk.BF16X3, "mixed_pivchol": ffk.BF16X3, "mixed_fp32": ffk.FP32}[arm]
+    SWITCH_BELOW, REFRESH = ffk.MIXED_SWITCH_BELOW, ffk.MIXED_REFRESH
     alpha, rep = ffk.pcg_solve(ctx, S, P, F, cfg.lam, tol=TOL, max_iter=50000, prec=prec, refresh_every=REFRESH,
                                escalate=True, switch_below=SWITCH_BELOW if mixed else 0.0)
     torch.cuda.synchronize()

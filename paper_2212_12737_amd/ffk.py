@@ -325,6 +325,15 @@ class Report:
     esc_iter: tuple = ()
 
 
+# Mixed-precision schedule used by the benchmark and the studies: FP64 products
+# until the recursive residual is below MIXED_SWITCH_BELOW |F|, the reduced
+# precision afterwards, and an FP64 true-residual refresh every MIXED_REFRESH
+# iterations (measured best on the M=21, N=2000 system: switch points 0.01 ..
+# 0.95, refresh intervals 5, 10 and 20).
+MIXED_SWITCH_BELOW = 0.7
+MIXED_REFRESH = 20
+
+
 def pcg_solve(ctx: Context, sys: System, P: Precond | None, F: torch.Tensor, lam: float, tol: float = 1e-6,
               max_iter: int = 0, prec: int = FP64, refresh_every: int = 10, escalate: bool = True,
               flexible: bool = False, timing: bool = False, hist_cap: int = 0, alpha: torch.Tensor | None = None,
