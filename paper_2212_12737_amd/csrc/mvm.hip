@@ -134,16 +134,10 @@ __global__ __launch_bounds__(256) void k_colsum_final(const double* __restrict__
 }
 
 // y_g = J_g^T G_g + shift v_g, one geometry per block (thread per atom).
-__global__ void k_jtg(const double* __restrict__ R, const double* __restrict__ G,
-                      const double* __restrict__ v, double shift, int M, int64_t D,
-                      double* __restrict__ y) {
-  extern __shared__ double sm[];
-  double* sR = sm;
-  double* sG = sm + 3 * M;
-  const int64_t g = blockIdx.x;
-  for (int i = threadIdx.x; i < 3 * M; i += blockDim.x) sR[i] = R[g * 3 * M + i];
-  for (int64_t i = threadIdx.x; i < D; i += blockDim.x) sG[i] = G[g * D + i];
-  __syncthreads();
+// y = J^T G + shift v for geometry g from its coordinates sR (3M) and its
+// row sG (D) of G, both in LDS
+__device__ inline void jtg_atoms(const double* sR, const double* sG, int64_t g, int M, const double* v,
+                                 double shift, double* y) {
   for (int a = threadIdx.x; a < M; a += blockDim.x) {
     double ax = 0.0, ay = 0.0, az = 0.0;
     const double xa = sR[3 * a], ya = sR[3 * a + 1], za = sR[3 * a + 2];
@@ -167,6 +161,49 @@ __global__ void k_jtg(const double* __restrict__ R, const double* __restrict__ G
     y[o + 1] = ay;
     y[o + 2] = az;
   }
+}
+
+__global__ void k_jtg(const double* __restrict__ R, const double* __restrict__ G,
+                      const double* __restrict__ v, double shift, int M, int64_t D,
+                      double* __restrict__ y) {
+  extern __shared__ double sm[];
+  double* sR = sm;
+  double* sG = sm + 3 * M;
+  const int64_t g = blockIdx.x;
+  for (int i = threadIdx.x; i < 3 * M; i += blockDim.x) sR[i] = R[g * 3 * M + i];
+  for (int64_t i = threadIdx.x; i < D; i += blockDim.x) sG[i] = G[g * D + i];
+  __syncthreads();
+  jtg_atoms(sR, sG, g, M, v, shift, y);
+}
+
+// The split-K reduction of GEMM 2 fused with J^T G: one block per geometry
+// forms its row of G = sum_z part_z + a0 s + w Xt in LDS (the arithmetic and
+// order of k_g_reduce) and applies J^T to it; G never goes to HBM.
+template <typename PT>
+__global__ void k_jtg_reduce(const PT* __restrict__ part, int splits, int64_t rows, const double* __restrict__ s,
+                             const double* __restrict__ Xt, const double* __restrict__ wpart, int ntn, double a0,
+                             const double* __restrict__ R, const double* __restrict__ v, double shift, int M,
+                             int64_t D, double* __restrict__ y) {
+  extern __shared__ double sm[];
+  double* sR = sm;
+  double* sG = sm + 3 * M;
+  __shared__ double wsh;
+  const int64_t g = blockIdx.x;
+  if (threadIdx.x == 0) {
+    double w = 0.0;
+    for (int q = 0; q < ntn; ++q) w += wpart[g * ntn + q];
+    wsh = w;
+  }
+  for (int i = threadIdx.x; i < 3 * M; i += blockDim.x) sR[i] = R[g * 3 * M + i];
+  __syncthreads();
+  const double w = wsh;
+  for (int64_t c = threadIdx.x; c < D; c += blockDim.x) {
+    double acc = 0.0;
+    for (int z = 0; z < splits; ++z) acc += (double)part[((int64_t)z * rows + g) * D + c];
+    sG[c] = acc + a0 * s[c] + w * Xt[g * D + c];
+  }
+  __syncthreads();
+  jtg_atoms(sR, sG, g, M, v, shift, y);
 }
 
 // ------------------------------------------------------------- epilogues ----
@@ -486,8 +523,14 @@ static int gemm2_splits(int64_t tiles, int64_t ktiles, int64_t N, int64_t D) {
   return best;
 }
 
+// K split count of GEMM 2 (1: G is written; above 1: the split partials are
+// left in a.part for k_jtg_reduce) and the row-sum partials per row of W.
+struct GemmOut {
+  int splits, ntn;
+};
+
 template <typename T, bool X3, typename CT, class TL1, class TL2>
-static void mvm_gemms_dma(const MvmArgs& a, int64_t Nr, int64_t Dk, int64_t Dr, const DmaOps& o, hipStream_t st,
+static GemmOut mvm_gemms_dma(const MvmArgs& a, int64_t Nr, int64_t Dk, int64_t Dr, const DmaOps& o, hipStream_t st,
                           hipEvent_t* ev) {
   const int64_t N = a.Nt, D = a.D;
   // FP32 and BF16: GEMM 1 computes P^T (EpiWT), so the row-sum partials of W
@@ -533,12 +576,8 @@ static void mvm_gemms_dma(const MvmArgs& a, int64_t Nr, int64_t Dk, int64_t Dr, 
     gemm_dma_kernel<T, TL2, X3, EpiPart<CT>><<<grid, TL2::NT, 0, st>>>(g, e);
     LAUNCHCHK();
     clk_end(CLK_GEMM2, st);
-    clk_begin(CLK_GEMM2_REDUCE, st);
-    k_g_reduce<CT><<<N, 256, 0, st>>>(static_cast<const CT*>(a.part), splits, N, D, a.s, a.Xt64, a.wpart, ntn,
-                                      a.a0, a.G);
-    LAUNCHCHK();
-    clk_end(CLK_GEMM2_REDUCE, st);
   }
+  return GemmOut{splits, ntn};
 }
 
 // Tile shapes: 64 x 64 (GEMM 1) and 128 x 128 (GEMM 2) by 4 waves for small
@@ -553,17 +592,17 @@ typedef DmaTile<256, 128, 4, 2, 3> TileLX3;    // 64 x 64 per wave, hi/lo operan
 constexpr int64_t kLargeN = 4096;
 
 template <typename T, bool X3, typename CT>
-static void mvm_gemms_for(const MvmArgs& a, int64_t Nr, int64_t Dk, int64_t Dr, const DmaOps& o, hipStream_t st,
+static GemmOut mvm_gemms_for(const MvmArgs& a, int64_t Nr, int64_t Dk, int64_t Dr, const DmaOps& o, hipStream_t st,
                           hipEvent_t* ev) {
   if (a.Nt < kLargeN) {
-    mvm_gemms_dma<T, X3, CT, TileM, TileS>(a, Nr, Dk, Dr, o, st, ev);
+    return mvm_gemms_dma<T, X3, CT, TileM, TileS>(a, Nr, Dk, Dr, o, st, ev);
   } else if constexpr (X3) {
-    mvm_gemms_dma<T, X3, CT, TileLX3, TileLX3>(a, Nr, Dk, Dr, o, st, ev);
+    return mvm_gemms_dma<T, X3, CT, TileLX3, TileLX3>(a, Nr, Dk, Dr, o, st, ev);
   } else if constexpr (sizeof(T) == 2) {
-    mvm_gemms_dma<T, X3, CT, TileL, TileL>(a, Nr, Dk, Dr, o, st, ev);
+    return mvm_gemms_dma<T, X3, CT, TileL, TileL>(a, Nr, Dk, Dr, o, st, ev);
   } else {
     // FP32 / FP64: MFMA-bound already at 128 x 128 (measured faster than the large tiles)
-    mvm_gemms_dma<T, X3, CT, TileS, TileS>(a, Nr, Dk, Dr, o, st, ev);
+    return mvm_gemms_dma<T, X3, CT, TileS, TileS>(a, Nr, Dk, Dr, o, st, ev);
   }
 }
 
@@ -641,6 +680,7 @@ void kernel_mvm_ev(ffk_system* s, const double* v, double* y, double shift, int 
   mark(ev, 2, st);
   MvmArgs a{N, N, D, s->a0, s->Xc.as<double>(), pd, w.s.as<double>(), w.wpart.as<double>(), w.G.as<double>(),
             w.part.get(), w.part.bytes()};
+  GemmOut go{1, 0};
   CoeffSet& cs = s->coef[prec];
   const int64_t Dk = rup(D, 64), Dr = pad_rows(D);
   DmaOps o{};
@@ -650,12 +690,12 @@ void kernel_mvm_ev(ffk_system* s, const double* v, double* y, double shift, int 
     o.Xh = s->Xp64.get(); o.XTh = s->XpT64.get();
     o.Uh = w.U64.get(); o.UTh = w.UT64.get();
     o.Wh = w.Wn64.get();
-    mvm_gemms_for<double, false, double>(a, Nr, Dk, Dr, o, st, ev);
+    go = mvm_gemms_for<double, false, double>(a, Nr, Dk, Dr, o, st, ev);
   } else if (prec == FFK_FP32) {
     o.Xh = s->Xp32.get(); o.XTh = s->XpT32.get();
     o.Uh = w.U32.get(); o.UTh = w.UT32.get();
     o.Wh = w.Wn32.get();
-    mvm_gemms_for<float, false, float>(a, Nr, Dk, Dr, o, st, ev);
+    go = mvm_gemms_for<float, false, float>(a, Nr, Dk, Dr, o, st, ev);
   } else {
     const bool x3 = prec == FFK_BF16X3;
     o.Xh = s->Xch.get(); o.XTh = s->XcTh.get();
@@ -666,15 +706,23 @@ void kernel_mvm_ev(ffk_system* s, const double* v, double* y, double shift, int 
       o.Ul = w.Ul.get(); o.UTl = w.UTl.get();
       o.dAl = cs.dA_lo.get();
       o.Wl = w.Wnl.get();
-      mvm_gemms_for<bf16_t, true, float>(a, Nr, Dk, Dr, o, st, ev);
+      go = mvm_gemms_for<bf16_t, true, float>(a, Nr, Dk, Dr, o, st, ev);
     } else {
-      mvm_gemms_for<bf16_t, false, float>(a, Nr, Dk, Dr, o, st, ev);
+      go = mvm_gemms_for<bf16_t, false, float>(a, Nr, Dk, Dr, o, st, ev);
     }
   }
   mark(ev, 4, st);
   const int tb = M <= 64 ? 64 : 128;
+  const size_t shj = (3 * M + D) * sizeof(double);
   clk_begin(CLK_JTG, st);
-  k_jtg<<<N, tb, (3 * M + D) * sizeof(double), st>>>(s->R.as<double>(), w.G.as<double>(), v, shift, M, D, y);
+  if (go.splits == 1)
+    k_jtg<<<N, tb, shj, st>>>(s->R.as<double>(), w.G.as<double>(), v, shift, M, D, y);
+  else if (prec == FFK_FP64)
+    k_jtg_reduce<double><<<N, 256, shj, st>>>(w.part.as<double>(), go.splits, N, w.s.as<double>(), s->Xc.as<double>(),
+                                             w.wpart.as<double>(), go.ntn, s->a0, s->R.as<double>(), v, shift, M, D, y);
+  else
+    k_jtg_reduce<float><<<N, 256, shj, st>>>(w.part.as<float>(), go.splits, N, w.s.as<double>(), s->Xc.as<double>(),
+                                            w.wpart.as<double>(), go.ntn, s->a0, s->R.as<double>(), v, shift, M, D, y);
   LAUNCHCHK();
   clk_end(CLK_JTG, st);
   mark(ev, 5, st);
