@@ -16,6 +16,7 @@ Modules
              scores (exact and pilot estimate)
   mlp     -- the score-predicting MLP: forward, backward, Adam
   rot     -- rule-of-thumb preconditioner size
+  symmetry -- the kernel symmetrized over a group of atom permutations
 
 Parity status of every function is listed in its module docstring.
 """
