@@ -94,6 +94,25 @@ ffk_status ffk_system_info(const ffk_system* sys, int64_t* N, int32_t* M, int64_
 /* Copy the (uncentred) descriptor X (N x D row-major float64) to X_dev. */
 ffk_status ffk_descriptor_export(ffk_ctx* ctx, const ffk_system* sys, double* X_dev, void* stream);
 
+/* Symmetrize the kernel of `sys` over a group of S atom permutations, the
+ * sGDML form of the paper's kernels (section 2.1):
+ *   k_S(R, R') = sum_q k(x(R), x(P_q R')),   (P_q R)_a = R_{p_q(a)},
+ * so the force-kernel block is sum_q J(R_i)^T H(x_i, x(P_q R_j)) J(P_q R_j)
+ * Pi_q (Pi_q permutes the atoms of a coordinate vector the same way).
+ * perms_host: S x M int32 in host memory, row q = p_q.  The rows must form a
+ * group: permutations of 0 .. M-1, no repeats, the identity included, closed
+ * under composition; otherwise FFK_ERR_ARG and nothing changes.  The group of
+ * the identity alone restores the plain kernel.  Afterwards every call on
+ * `sys` uses K_S: ffk_kernel_mvm (FP64 only; other precisions return
+ * FFK_ERR_ARG), ffk_kernel_columns, ffk_kernel_diag, selection, the
+ * preconditioner, PCG, the exact leverage scores, and ffk_kernel_predict
+ * with `sys` as the training system.  A product costs S rectangular FP64
+ * products; the coefficients of each pair are kept between products.
+ * Finding the permutations (sGDML matches the molecular graph) is left to
+ * the caller. */
+ffk_status ffk_system_set_symmetries(ffk_ctx* ctx, ffk_system* sys, const int32_t* perms_host, int32_t S,
+                                     void* stream);
+
 /* y = K v + shift * v for the training system (v, y: n float64), with the
  * contractions in precision `prec`.  Matrix free: U = J v (N x D),
  * P = X_c U^T, W = B o (P - 1 diag(P)^T), G = a(0) 1 1^T U + dA U - W X_c +

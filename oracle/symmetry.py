@@ -79,11 +79,14 @@ def dense_sym_kernel(R: np.ndarray, perms, sigma: float) -> np.ndarray:
     return K
 
 
-def sym_kernel_mvm(R: np.ndarray, perms, v: np.ndarray, sigma: float) -> np.ndarray:
-    """Matrix-free K_S v = sum_q K(R, P_q R) (Pi_q v), with the plain product."""
+def sym_kernel_mvm(R: np.ndarray, perms, v: np.ndarray, sigma: float, R_tgt=None) -> np.ndarray:
+    """Matrix-free K_S(R_tgt, R) v = sum_q K(R_tgt, P_q R) (Pi_q v), with the
+    plain product (R_tgt defaults to R: the training product; other targets
+    give the prediction of a symmetrized model)."""
     N, M, _ = R.shape
+    T = R if R_tgt is None else R_tgt
     V = v.reshape(N, M, 3)
-    y = np.zeros(N * 3 * M)
+    y = np.zeros(T.shape[0] * 3 * M)
     for p in perms:
-        y += ok.kernel_mvm(R, permute_geometries(R, p), V[:, np.asarray(p), :].reshape(-1), sigma)
+        y += ok.kernel_mvm(T, permute_geometries(R, p), V[:, np.asarray(p), :].reshape(-1), sigma)
     return y

@@ -102,6 +102,15 @@ ffk_status ffk_system_info(const ffk_system* s, int64_t* N, int32_t* M, int64_t*
   return FFK_OK;
 }
 
+ffk_status ffk_system_set_symmetries(ffk_ctx* ctx, ffk_system* s, const int32_t* perms, int32_t nperm,
+                                     void* stream) {
+  if (!ctx || !s) return FFK_ERR_ARG;
+  return guarded(ctx, [&]() {
+    set_symmetries(s, perms, nperm, S(stream));
+    return FFK_OK;
+  });
+}
+
 ffk_status ffk_descriptor_export(ffk_ctx* ctx, const ffk_system* s, double* X_dev, void* stream) {
   if (!ctx || !s || !X_dev) return FFK_ERR_ARG;
   return guarded(ctx, [&]() {

@@ -24,11 +24,15 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
+// Targets (rows) come from R, X; the source geometry of each column from
+// Rs, Xs (the same arrays for a plain kernel, a permuted copy for a
+// symmetrized one).  With accumulate the values are added to out.
 __global__ __launch_bounds__(256) void k_columns(const double* __restrict__ R, const double* __restrict__ X,
+                                                 const double* __restrict__ Rs, const double* __restrict__ Xs,
                                                  const int* __restrict__ pairs, int M, int64_t D,
                                                  const int64_t* __restrict__ cols, int64_t k,
                                                  double* __restrict__ out, int64_t ldo, double shift,
-                                                 double inv_len, double a0, double bcoef) {
+                                                 double inv_len, double a0, double bcoef, int accumulate) {
   extern __shared__ double sm[];
   const int nw = blockDim.x >> 6;   // waves per block (1, 2 or 4)
   double* sRi = sm;                 // 3M
@@ -69,12 +73,12 @@ __global__ __launch_bounds__(256) void k_columns(const double* __restrict__ R, c
       p = loc / 3;
       t = loc % 3;
       for (int64_t e = lane; e < D; e += 64) {      // d = x_i - x_g and |d|^2
-        const double dd = Xi[e] - X[g * D + e];
+        const double dd = Xi[e] - Xs[g * D + e];
         dW[e] = dd;
         r2 += dd * dd;
       }
       r2 = wave_sum(r2);
-      const double* Rg = R + g * m3;
+      const double* Rg = Rs + g * m3;
       for (int b = lane; b < M; b += 64) {          // u on the pairs {p, b}
         double u = 0.0;
         if (b != p) {
@@ -116,17 +120,27 @@ __global__ __launch_bounds__(256) void k_columns(const double* __restrict__ R, c
         }
         const int64_t row = i * m3 + 3 * q;
         double* o = out + cidx * ldo + row;
-        o[0] = a * ux + bdu * jx + (row == col ? shift : 0.0);
-        o[1] = a * uy + bdu * jy + (row + 1 == col ? shift : 0.0);
-        o[2] = a * uz + bdu * jz + (row + 2 == col ? shift : 0.0);
+        const double v0 = a * ux + bdu * jx + (row == col ? shift : 0.0);
+        const double v1 = a * uy + bdu * jy + (row + 1 == col ? shift : 0.0);
+        const double v2 = a * uz + bdu * jz + (row + 2 == col ? shift : 0.0);
+        if (accumulate) {
+          o[0] += v0;
+          o[1] += v1;
+          o[2] += v2;
+        } else {
+          o[0] = v0;
+          o[1] = v1;
+          o[2] = v2;
+        }
       }
     }
     __syncthreads();
   }
 }
 
-void kernel_columns(const ffk_system* s, const int64_t* cols, int64_t k, double* out, int64_t ldo, double shift,
-                    hipStream_t st) {
+// Columns of K(s, src) in the source numbering (src = s for the plain kernel).
+void kernel_columns_src(const ffk_system* s, const ffk_system* src, const int64_t* cols, int64_t k, double* out,
+                        int64_t ldo, double shift, bool accumulate, hipStream_t st) {
   if (k <= 0) return;
   const int M = s->M;
   const int64_t D = s->D;
@@ -144,11 +158,18 @@ void kernel_columns(const ffk_system* s, const int64_t* cols, int64_t k, double*
   for (int64_t c0 = 0; c0 < k; c0 += per_launch) {
     const int64_t kc = std::min(per_launch, k - c0);
     dim3 grid((unsigned)s->N, (unsigned)cdiv(kc, COLS_PER_BLOCK));
-    k_columns<<<grid, 64 * nw, bytes(nw), st>>>(s->R.as<double>(), s->X.as<double>(), s->pairs.as<int>(), M, D,
-                                                cols + c0, kc, out + c0 * ldo, ldo, shift, sqrt(5.0) / s->sigma,
-                                                s->a0, s->bcoef);
+    k_columns<<<grid, 64 * nw, bytes(nw), st>>>(s->R.as<double>(), s->X.as<double>(), src->R.as<double>(),
+                                                src->X.as<double>(), s->pairs.as<int>(), M, D, cols + c0, kc,
+                                                out + c0 * ldo, ldo, shift, sqrt(5.0) / s->sigma, s->a0, s->bcoef,
+                                                accumulate ? 1 : 0);
     LAUNCHCHK();
   }
+}
+
+void kernel_columns(const ffk_system* s, const int64_t* cols, int64_t k, double* out, int64_t ldo, double shift,
+                    hipStream_t st) {
+  if (!s->sym.empty()) sym_columns(s, cols, k, out, ldo, shift, st);
+  else kernel_columns_src(s, s, cols, k, out, ldo, shift, false, st);
 }
 
 // diag(K)_{3Mg + 3p + t} = a(0) sum_{b != p} ((R_gp - R_gb)_t / r^3)^2
@@ -174,6 +195,10 @@ __global__ void k_diag(const double* __restrict__ R, int64_t N, int M, double a0
 }
 
 void kernel_diag(const ffk_system* s, double* d, hipStream_t st) {
+  if (!s->sym.empty()) {
+    sym_diag(s, d, st);
+    return;
+  }
   k_diag<<<cdiv(s->N * s->M, 256), 256, 0, st>>>(s->R.as<double>(), s->N, s->M, s->a0, d);
   LAUNCHCHK();
 }

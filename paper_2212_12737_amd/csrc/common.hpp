@@ -162,6 +162,16 @@ struct MvmWork {
 
 }  // namespace ffk
 
+namespace ffk {
+// Fixed coefficients and workspaces of a rectangular product K(tgt, src)
+// whose geometries do not change (a permuted copy of a symmetrized system,
+// as the source, against the system itself); valid while tgt is the target.
+struct RectCache {
+  const ffk_system* tgt = nullptr;
+  DBuf Xt, sqt, dA, B, Wn, U, pd, sv, cpart, wpart, G, part;
+};
+}  // namespace ffk
+
 struct ffk_system {
   ffk_ctx* ctx = nullptr;
   int64_t N = 0;
@@ -184,6 +194,15 @@ struct ffk_system {
   ffk::CoeffSet coef[4];    // indexed by ffk_precision
   ffk::MvmWork work;
   double max_diag = -1.0;   // max diag(K), computed on demand
+  // Symmetrized kernel (sum over a group of atom permutations p_q): the
+  // systems of the permuted geometries P_q R, the permutations (S x M) and
+  // their inverses on the device, and a work vector.  Empty: the plain kernel.
+  std::vector<std::unique_ptr<ffk_system>> sym;
+  std::vector<int32_t> sym_perm_host;
+  ffk::DBuf sym_perm, sym_pinv;
+  ffk::DBuf sym_work;
+  int sym_identity = 0;     // index of the identity in the group
+  ffk::RectCache rect;      // used when this system is a permuted copy
 };
 
 struct ffk_precond {
@@ -216,7 +235,21 @@ namespace ffk {
 
 // ---------------------------------------------------- internal interfaces ----
 // descriptor.hip
-void descriptor_build(ffk_system* sys, const double* R, hipStream_t st);
+void descriptor_build(ffk_system* sys, const double* R, hipStream_t st, bool coefficients = true);
+// symmetry.hip -- the kernel symmetrized over a group of atom permutations
+void set_symmetries(ffk_system* sys, const int32_t* perms_host, int S, hipStream_t st);
+void sym_mvm(ffk_system* sys, const double* v, double* y, double shift, hipStream_t st);
+void sym_columns(const ffk_system* s, const int64_t* cols, int64_t k, double* out, int64_t ldo, double shift,
+                 hipStream_t st);
+void sym_diag(const ffk_system* s, double* d, hipStream_t st);
+// columns.hip -- columns of K(s, src) in the numbering of src (targets from s)
+void kernel_columns_src(const ffk_system* s, const ffk_system* src, const int64_t* cols, int64_t k, double* out,
+                        int64_t ldo, double shift, bool accumulate, hipStream_t st);
+// mvm.hip -- y (+)= K(tgt, src) alpha on the FP64 engine; with shift_v, the
+// first (non-accumulating) pass also adds shift * shift_v
+void rect_mvm(const ffk_system* src, const ffk_system* tgt, const double* alpha, double* y, bool accumulate,
+              const double* shift_v, double shift, RectCache* cache, hipStream_t st);
+void permute_atoms(const double* a, const int32_t* p, int64_t N, int M, double* out, hipStream_t st);
 void ensure_coeffs(ffk_system* sys, int prec, hipStream_t st);
 void ensure_lowp_descriptor(ffk_system* sys, int prec, hipStream_t st);
 

@@ -91,7 +91,7 @@ struct EpiCoeff {
   }
 };
 
-void descriptor_build(ffk_system* s, const double* R, hipStream_t st) {
+void descriptor_build(ffk_system* s, const double* R, hipStream_t st, bool coefficients) {
   const int64_t N = s->N, D = s->D;
   const int M = s->M;
   // pair table
@@ -123,7 +123,7 @@ void descriptor_build(ffk_system* s, const double* R, hipStream_t st) {
   k_center<<<N, 256, 0, st>>>(s->X.as<double>(), s->xmean.as<double>(), D, s->Xc.as<double>(),
                               s->sqn.as<double>());
   LAUNCHCHK();
-  ensure_coeffs(s, FFK_FP64, st);
+  if (coefficients) ensure_coeffs(s, FFK_FP64, st);
 }
 
 // ------------------------------------------------------------ conversions ----

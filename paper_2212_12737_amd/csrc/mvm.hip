@@ -137,7 +137,7 @@ __global__ __launch_bounds__(256) void k_colsum_final(const double* __restrict__
 // y = J^T G + shift v for geometry g from its coordinates sR (3M) and its
 // row sG (D) of G, both in LDS
 __device__ inline void jtg_atoms(const double* sR, const double* sG, int64_t g, int M, const double* v,
-                                 double shift, double* y) {
+                                 double shift, double* y, bool accumulate = false) {
   for (int a = threadIdx.x; a < M; a += blockDim.x) {
     double ax = 0.0, ay = 0.0, az = 0.0;
     const double xa = sR[3 * a], ya = sR[3 * a + 1], za = sR[3 * a + 2];
@@ -157,15 +157,22 @@ __device__ inline void jtg_atoms(const double* sR, const double* sG, int64_t g, 
       ay += shift * v[o + 1];
       az += shift * v[o + 2];
     }
-    y[o] = ax;
-    y[o + 1] = ay;
-    y[o + 2] = az;
+    if (accumulate) {
+      y[o] += ax;
+      y[o + 1] += ay;
+      y[o + 2] += az;
+    } else {
+      y[o] = ax;
+      y[o + 1] = ay;
+      y[o + 2] = az;
+    }
   }
 }
 
+// y = J^T G + shift v, or y += J^T G with accumulate (then v is unused)
 __global__ void k_jtg(const double* __restrict__ R, const double* __restrict__ G,
                       const double* __restrict__ v, double shift, int M, int64_t D,
-                      double* __restrict__ y) {
+                      double* __restrict__ y, int accumulate = 0) {
   extern __shared__ double sm[];
   double* sR = sm;
   double* sG = sm + 3 * M;
@@ -173,7 +180,7 @@ __global__ void k_jtg(const double* __restrict__ R, const double* __restrict__ G
   for (int i = threadIdx.x; i < 3 * M; i += blockDim.x) sR[i] = R[g * 3 * M + i];
   for (int64_t i = threadIdx.x; i < D; i += blockDim.x) sG[i] = G[g * D + i];
   __syncthreads();
-  jtg_atoms(sR, sG, g, M, v, shift, y);
+  jtg_atoms(sR, sG, g, M, accumulate ? nullptr : v, shift, y, accumulate != 0);
 }
 
 // The split-K reduction of GEMM 2 fused with J^T G: one block per geometry
@@ -648,6 +655,13 @@ static void ensure_work(ffk_system* s, int prec, hipStream_t st) {
 void kernel_mvm_ev(ffk_system* s, const double* v, double* y, double shift, int prec, hipStream_t st,
                    hipEvent_t* ev) {
   require(prec >= FFK_FP64 && prec <= FFK_BF16X3, "kernel_mvm: unknown precision");
+  if (!s->sym.empty()) {
+    require(prec == FFK_FP64, "kernel_mvm: a symmetrized kernel runs its products in FP64");
+    mark(ev, 0, st);
+    sym_mvm(s, v, y, shift, st);
+    for (int i = 1; i <= 5; ++i) mark(ev, i, st);
+    return;
+  }
   ensure_coeffs(s, prec, st);
   ensure_lowp_descriptor(s, prec, st);
   ensure_work(s, prec, st);
@@ -772,47 +786,80 @@ __global__ void k_center_with(const double* __restrict__ X, const double* __rest
   if (threadIdx.x == 0) sqn[g] = red[0];
 }
 
-void kernel_predict(const ffk_system* tr, const ffk_system* te, const double* alpha, double* F, hipStream_t st) {
-  require(tr->M == te->M, "kernel_predict: train and test molecules differ in size");
-  require(tr->sigma == te->sigma, "kernel_predict: sigma differs");
+// y (+)= K(tgt, src) alpha on the scalar FP64 engine (rectangular: targets
+// and sources are different systems of the same molecule).  The target
+// descriptors are centred with the source mean (the kernel depends on
+// differences only).  With a cache, the coefficients of the pair and the
+// workspaces are kept for the next call with the same target.
+void rect_mvm(const ffk_system* tr, const ffk_system* te, const double* alpha, double* F, bool accumulate,
+              const double* shift_v, double shift, RectCache* cache, hipStream_t st) {
+  require(tr->M == te->M, "kernel product: the two systems differ in molecule size");
+  require(tr->sigma == te->sigma, "kernel product: sigma differs");
   const int64_t Ns = tr->N, Nt = te->N, D = tr->D;
   const int M = tr->M;
   const int nblk = cdiv(Ns, GT);
-  DBuf U(Ns * D * 8), pd(Ns * 8), sv(D * 8), cpart((int64_t)nblk * D * 8);
-  DBuf Xt(Nt * D * 8), sqt(Nt * 8), dA(Nt * Ns * 8), B(Nt * Ns * 8), Wn(Nt * Ns * 8);
   const int ntn = cdiv(Ns, 128);
-  DBuf wpart(Nt * ntn * 8), G(Nt * D * 8), part(part_budget(Nt, D));
-  k_jv_tile<0><<<nblk, 256, (size_t)2 * GT * 3 * M * sizeof(double), st>>>(
-      tr->R.as<double>(), tr->pairs.as<int>(), alpha, tr->Xc.as<double>(), Ns, M, D, U.get(), nullptr, D, nullptr,
-      nullptr, 0, pd.as<double>(), cpart.as<double>());
-  LAUNCHCHK();
-  clk_begin(CLK_COLSUM, st);
-  k_colsum_final<<<cdiv(D, 64), 256, 0, st>>>(cpart.as<double>(), nblk, D, sv.as<double>());
-  LAUNCHCHK();
-  clk_end(CLK_COLSUM, st);
-  k_center_with<<<Nt, 256, 0, st>>>(te->X.as<double>(), tr->xmean.as<double>(), D, Xt.as<double>(), sqt.as<double>());
-  LAUNCHCHK();
-  {
+  RectCache local;
+  RectCache& c = cache ? *cache : local;
+  if (!cache || c.tgt != te) {
+    c.tgt = nullptr;
+    c.U.alloc(Ns * D * 8);
+    c.pd.alloc(Ns * 8);
+    c.sv.alloc(D * 8);
+    c.cpart.alloc((int64_t)nblk * D * 8);
+    c.Xt.alloc(Nt * D * 8);
+    c.sqt.alloc(Nt * 8);
+    c.dA.alloc(Nt * Ns * 8);
+    c.B.alloc(Nt * Ns * 8);
+    c.Wn.alloc(Nt * Ns * 8);
+    c.wpart.alloc(Nt * ntn * 8);
+    c.G.alloc(Nt * D * 8);
+    c.part.alloc(part_budget(Nt, D));
+    k_center_with<<<Nt, 256, 0, st>>>(te->X.as<double>(), tr->xmean.as<double>(), D, c.Xt.as<double>(),
+                                      c.sqt.as<double>());
+    LAUNCHCHK();
     ScalarArgs<double> g{};
     g.M = (int)Nt;
     g.N = (int)Ns;
     g.nseg = 1;
-    g.seg[0] = SegS<double>{Xt.as<double>(), D, 1, tr->Xc.as<double>(), D, 1, (int)D};
-    EpiCoeffRect e{sqt.as<double>(), tr->sqn.as<double>(), dA.as<double>(), B.as<double>(), (int)Nt, (int)Ns,
-                   sqrt(5.0) / tr->sigma, tr->a0, tr->bcoef};
+    g.seg[0] = SegS<double>{c.Xt.as<double>(), D, 1, tr->Xc.as<double>(), D, 1, (int)D};
+    EpiCoeffRect e{c.sqt.as<double>(), tr->sqn.as<double>(), c.dA.as<double>(), c.B.as<double>(), (int)Nt,
+                   (int)Ns, sqrt(5.0) / tr->sigma, tr->a0, tr->bcoef};
     gemm_scalar_kernel<double, 128, 128, 16, true, true, EpiCoeffRect><<<dim3(ntn, cdiv(Nt, 128)), 256, 0, st>>>(g, e);
     LAUNCHCHK();
+    if (cache) c.tgt = te;
   }
-  MvmArgs a{Nt, Ns, D, tr->a0, Xt.as<double>(), pd.as<double>(), sv.as<double>(), wpart.as<double>(), G.as<double>(),
-            part.get(), part.bytes()};
-  mvm_gemms_scalar<double>(a, Xt.as<double>(), tr->Xc.as<double>(), U.as<double>(), dA.as<double>(), B.as<double>(),
-                           Wn.as<double>(), st, nullptr);
-  const int tb = M <= 64 ? 64 : 128;
-  clk_begin(CLK_JTG, st);
-  k_jtg<<<Nt, tb, (3 * M + D) * sizeof(double), st>>>(te->R.as<double>(), G.as<double>(), nullptr, 0.0, M, D, F);
+  k_jv_tile<0><<<nblk, 256, (size_t)2 * GT * 3 * M * sizeof(double), st>>>(
+      tr->R.as<double>(), tr->pairs.as<int>(), alpha, tr->Xc.as<double>(), Ns, M, D, c.U.get(), nullptr, D, nullptr,
+      nullptr, 0, c.pd.as<double>(), c.cpart.as<double>());
   LAUNCHCHK();
-  clk_end(CLK_JTG, st);
-  HIPCHK(hipStreamSynchronize(st));   // temporaries are freed on return
+  k_colsum_final<<<cdiv(D, 64), 256, 0, st>>>(c.cpart.as<double>(), nblk, D, c.sv.as<double>());
+  LAUNCHCHK();
+  MvmArgs a{Nt, Ns, D, tr->a0, c.Xt.as<double>(), c.pd.as<double>(), c.sv.as<double>(), c.wpart.as<double>(),
+            c.G.as<double>(), c.part.get(), c.part.bytes()};
+  mvm_gemms_scalar<double>(a, c.Xt.as<double>(), tr->Xc.as<double>(), c.U.as<double>(), c.dA.as<double>(),
+                           c.B.as<double>(), c.Wn.as<double>(), st, nullptr);
+  const int tb = M <= 64 ? 64 : 128;
+  k_jtg<<<Nt, tb, (3 * M + D) * sizeof(double), st>>>(te->R.as<double>(), c.G.as<double>(), shift_v, shift, M, D,
+                                                      F, accumulate ? 1 : 0);
+  LAUNCHCHK();
+  if (!cache) HIPCHK(hipStreamSynchronize(st));   // the temporaries are freed on return
+}
+
+// F = K(test, train) alpha; a symmetrized training system predicts with
+// sum_q K(test, train_q) (Pi_q alpha), train_q its permuted copies
+void kernel_predict(const ffk_system* tr, const ffk_system* te, const double* alpha, double* F, hipStream_t st) {
+  if (tr->sym.empty()) {
+    rect_mvm(tr, te, alpha, F, false, nullptr, 0.0, nullptr, st);
+    return;
+  }
+  DBuf aq(tr->n * 8);
+  const int M = tr->M;
+  for (size_t q = 0; q < tr->sym.size(); ++q) {
+    permute_atoms(alpha, tr->sym_perm.as<int32_t>() + q * M, tr->N, M, aq.as<double>(), st);
+    rect_mvm(tr->sym[q].get(), te, aq.as<double>(), F, q > 0, nullptr, 0.0, nullptr, st);
+  }
+  HIPCHK(hipStreamSynchronize(st));
 }
 
 }  // namespace ffk

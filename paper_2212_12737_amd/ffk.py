@@ -92,6 +92,7 @@ _SIGS = {
     "ffk_mlp_prepare_inputs": (I32, [P, P, P, P, I32, P]),
     "ffk_mlp_fit_norm": (I32, [P, P, P, I64, P]),
     "ffk_rule_of_thumb": (I64, [I64, DBL, DBL]),
+    "ffk_system_set_symmetries": (I32, [P, P, P, I32, P]),
     "ffk_rot_fit": (I32, [P, P, I32, I64, P, P]),
     "ffk_rule_of_thumb_calibrated": (I64, [I64, DBL, DBL, DBL, DBL, DBL]),
 }
@@ -227,6 +228,16 @@ def clock_read(ctx: Context) -> dict:
         ctx.check(lib().ffk_clock_read(ctx.h, i, ctypes.byref(ms), ctypes.byref(cnt)), "clock_read")
         out[name] = (ms.value, cnt.value)
     return out
+
+
+def set_symmetries(ctx: Context, sys: System, perms, stream=None) -> None:
+    """Symmetrize the kernel of sys over a group of atom permutations (S x M rows p_q)."""
+    import numpy as np
+    P = np.ascontiguousarray(np.asarray(perms, dtype=np.int32))
+    if P.ndim != 2 or P.shape[1] != sys.M:
+        raise ValueError("perms must be S x M")
+    ctx.check(lib().ffk_system_set_symmetries(ctx.h, sys.h, P.ctypes.data, P.shape[0], _stream(stream)),
+              "set_symmetries")
 
 
 def kernel_predict(ctx: Context, train: System, test: System, alpha: torch.Tensor, stream=None) -> torch.Tensor:
