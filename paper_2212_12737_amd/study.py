@@ -6,6 +6,7 @@ labels of smaller systems of the same molecule.
     python -m paper_2212_12737_amd.study compare --config m21_n10000 --labels DIR [--steps 3000]
     python -m paper_2212_12737_amd.study rot --config m21_n2000 [--sweep-N 250,500,1000]
     python -m paper_2212_12737_amd.study spectrum --config m21_n2000 [--spec-N 100 --spec-ks 100,400,1600]
+    python -m paper_2212_12737_amd.study sym --config m21_n2000 [--sym-N 1000 --sym-orders 1,2,4,8]
 
 `labels` computes the exact labels (dense FP64 Cholesky on the GPU, about a
 minute per N = 2000 system) and saves one .npy per training system, so they
@@ -15,7 +16,8 @@ for the preconditioner size (section 4.3): a k-sweep of PCG iterations on
 small systems, the power-law fit, and the workload solved at the predicted
 sizes and over a grid of k.  `spectrum` compares the spectrum of the
 preconditioned matrix across strategies and sizes with the optimal rank-k
-preconditioner (section 4.1), on a small system.  Every step of the solver
+preconditioner (section 4.1), on a small system.  `sym` times the kernel
+symmetrized over groups of atom permutations (product and solve).  Every step of the solver
 runs in libffkrr; the dense eigen-analysis of `spectrum` runs on the host.
 """
 from __future__ import annotations
@@ -254,9 +256,55 @@ def spectrum(ctx, config, N, ks, strategies, top):
     return out
 
 
+def transposition_group(M, t):
+    """The group of order 2^t generated by the disjoint swaps (0 1), (2 3), ...,
+    as S x M atom permutations (identity first)."""
+    rows = []
+    for mask in range(1 << t):
+        p = list(range(M))
+        for j in range(t):
+            if mask >> j & 1:
+                p[2 * j], p[2 * j + 1] = p[2 * j + 1], p[2 * j]
+        rows.append(p)
+    return np.array(rows, dtype=np.int32)
+
+
+def symmetry(ctx, config, N, orders, reps):
+    """The kernel symmetrized over groups of atom permutations (sGDML form):
+    FP64 product time against the group order, and a PCG solve (uniform
+    columns, FP64 products and factor) with the symmetrized kernel."""
+    synth, cfg = _config(config)
+    s, S = _system(ctx, synth, cfg, N, cfg.disp_seed)
+    F = torch.as_tensor(s.flat_forces(), device=ctx.torch_device)
+    v = torch.ones(S.n, dtype=torch.float64, device=ctx.torch_device)
+    for order in orders:
+        t = int(round(np.log2(order)))
+        ffk.set_symmetries(ctx, S, transposition_group(S.M, t))
+        ffk.kernel_mvm(ctx, S, v)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            ffk.kernel_mvm(ctx, S, v)
+        torch.cuda.synchronize()
+        t_mvm = (time.perf_counter() - t0) / reps
+        t0 = time.perf_counter()
+        idx = ffk.nystrom_select(ctx, S, "uniform", cfg.k, seed=cfg.sel_seed)
+        P = ffk.precond_build(ctx, S, idx, cfg.lam, store=ffk.FP64)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        _, rep = ffk.pcg_solve(ctx, S, P, F, cfg.lam, tol=1e-6, max_iter=20000, prec=ffk.FP64)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        print(json.dumps({"group_order": order, "n": S.n, "k": cfg.k, "product_ms": 1e3 * t_mvm,
+                          "build_s": t1 - t0, "pcg_iters": rep.iters, "pcg_s": t2 - t1, "status": rep.status,
+                          "rel_res_true": rep.rel_res_true}), flush=True)
+        del P
+    ffk.set_symmetries(ctx, S, transposition_group(S.M, 0))
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("mode", choices=["labels", "compare", "rot", "spectrum"])
+    ap.add_argument("mode", choices=["labels", "compare", "rot", "spectrum", "sym"])
     ap.add_argument("--config", default="m21_n10000")
     ap.add_argument("--out", default="study_labels")
     ap.add_argument("--labels", default="study_labels")
@@ -270,6 +318,8 @@ def main(argv=None):
     ap.add_argument("--spec-N", type=int, default=100, help="spectrum: geometries of the system")
     ap.add_argument("--spec-ks", default="100,400,1600", help="spectrum: preconditioner sizes")
     ap.add_argument("--spec-out", default=None, help="spectrum: .npz with the dominant eigenvalues")
+    ap.add_argument("--sym-N", type=int, default=1000, help="sym: geometries of the system")
+    ap.add_argument("--sym-orders", default="1,2,4,8", help="sym: group orders (powers of two)")
     a = ap.parse_args(argv)
     ctx = ffk.create(0)
     ints = lambda t: [int(x) for x in t.split(",")]
@@ -279,6 +329,8 @@ def main(argv=None):
         compare(ctx, a.config, a.labels, a.steps, (a.arms or "learned,pivchol,uniform,leverage").split(","))
     elif a.mode == "rot":
         rule_of_thumb(ctx, a.config, ints(a.sweep_N), ints(a.ks), ints(a.grid), (a.arms or "fp64,mixed").split(","))
+    elif a.mode == "sym":
+        symmetry(ctx, a.config, a.sym_N, ints(a.sym_orders), 5)
     else:
         out = spectrum(ctx, a.config, a.spec_N, ints(a.spec_ks), (a.arms or "uniform,leverage,pivchol").split(","), 150)
         if a.spec_out:
