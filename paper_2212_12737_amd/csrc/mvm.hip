@@ -112,25 +112,26 @@ __global__ __launch_bounds__(256) void k_jv_tile(const double* __restrict__ R, c
   }
 }
 
-// s = sum of the per-block column partials (nblk x D): 64 columns x 4 row
-// groups per block, combined in a fixed order.
+// s = sum of the per-block column partials (nblk x D): 16 columns per block;
+// the 16 lanes of a column take partials q, q + 16, ... and combine by a
+// fixed butterfly.
 __global__ __launch_bounds__(256) void k_colsum_final(const double* __restrict__ part, int nblk, int64_t D,
                                                       double* __restrict__ s) {
-  __shared__ double sh[4][64];
-  const int c = threadIdx.x & 63, rg = threadIdx.x >> 6;
-  const int64_t col = (int64_t)blockIdx.x * 64 + c;
+  const int64_t col = (int64_t)blockIdx.x * 16 + (threadIdx.x >> 4);
+  const int q = threadIdx.x & 15;
   double a0 = 0.0, a1 = 0.0;
   if (col < D) {
-    int i = rg;
-    for (; i + 4 < nblk; i += 8) {
+    int i = q;
+    for (; i + 16 < nblk; i += 32) {
       a0 += part[(int64_t)i * D + col];
-      a1 += part[(int64_t)(i + 4) * D + col];
+      a1 += part[(int64_t)(i + 16) * D + col];
     }
     if (i < nblk) a0 += part[(int64_t)i * D + col];
   }
-  sh[rg][c] = a0 + a1;
-  __syncthreads();
-  if (rg == 0 && col < D) s[col] = (sh[0][c] + sh[1][c]) + (sh[2][c] + sh[3][c]);
+  double t = a0 + a1;
+#pragma unroll
+  for (int off = 8; off >= 1; off >>= 1) t += __shfl_xor(t, off);
+  if (q == 0 && col < D) s[col] = t;
 }
 
 // y_g = J_g^T G_g + shift v_g, one geometry per block (thread per atom).
@@ -688,7 +689,7 @@ void kernel_mvm_ev(ffk_system* s, const double* v, double* y, double shift, int 
   clk_end(CLK_JV, st);
   mark(ev, 1, st);
   clk_begin(CLK_COLSUM, st);
-  k_colsum_final<<<cdiv(D, 64), 256, 0, st>>>(cp, nblk, D, w.s.as<double>());
+  k_colsum_final<<<cdiv(D, 16), 256, 0, st>>>(cp, nblk, D, w.s.as<double>());
   LAUNCHCHK();
   clk_end(CLK_COLSUM, st);
   mark(ev, 2, st);
@@ -833,7 +834,7 @@ void rect_mvm(const ffk_system* tr, const ffk_system* te, const double* alpha, d
       tr->R.as<double>(), tr->pairs.as<int>(), alpha, tr->Xc.as<double>(), Ns, M, D, c.U.get(), nullptr, D, nullptr,
       nullptr, 0, c.pd.as<double>(), c.cpart.as<double>());
   LAUNCHCHK();
-  k_colsum_final<<<cdiv(D, 64), 256, 0, st>>>(c.cpart.as<double>(), nblk, D, c.sv.as<double>());
+  k_colsum_final<<<cdiv(D, 16), 256, 0, st>>>(c.cpart.as<double>(), nblk, D, c.sv.as<double>());
   LAUNCHCHK();
   MvmArgs a{Nt, Ns, D, tr->a0, c.Xt.as<double>(), c.pd.as<double>(), c.sv.as<double>(), c.wpart.as<double>(),
             c.G.as<double>(), c.part.get(), c.part.bytes()};
