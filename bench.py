@@ -261,6 +261,9 @@ def main(argv=None) -> int:
     ap.add_argument("--kernels-only", type=int, default=0,
                     help="counter-collection mode: build once, run this many preconditioner applies and products, "
                          "plus a plain copy of known size for calibration; prints no JSON line")
+    ap.add_argument("--mvm-only", type=int, default=0,
+                    help="counter-collection mode: this many kernel products per precision at each --mvm-configs "
+                         "shape (after one untimed product each); prints no JSON line")
     a = ap.parse_args(argv)
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if a.gpus != 1 or world != 1:
@@ -280,6 +283,23 @@ def main(argv=None) -> int:
     n = R.numel()
     log("workload %s: M=%d N=%d D=%d n=%d k=%d lambda=%g strategy=%s"
         % (cfg.name, cfg.M, cfg.N, cfg.D, n, cfg.k, cfg.lam, cfg.strategy))
+
+    if a.mvm_only:
+        for c in [c for c in a.mvm_configs.split(",") if c]:
+            cc = synth.CONFIGS[c]
+            sc = synth.config_system(cc)
+            Sc = ffk.descriptor_build(ctx, torch.as_tensor(sc.R, device="cuda"), cc.sigma)
+            vc = torch.as_tensor(synth.random_vectors(Sc.n, 5), device="cuda")
+            for prec in ("bf16", "bf16x3", "fp32", "fp64"):
+                ffk.kernel_mvm(ctx, Sc, vc, prec=ffk.PRECISIONS[prec])
+                torch.cuda.synchronize()
+                log("products %s %s: %d after one untimed" % (c, prec, a.mvm_only))
+                for _ in range(a.mvm_only):
+                    ffk.kernel_mvm(ctx, Sc, vc, prec=ffk.PRECISIONS[prec])
+                torch.cuda.synchronize()
+            del Sc, vc
+        log("mvm-only done")
+        return 0
 
     if a.kernels_only:
         x = torch.empty(1 << 27, dtype=torch.float64, device="cuda").normal_()
