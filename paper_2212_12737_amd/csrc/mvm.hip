@@ -22,13 +22,15 @@ static int64_t rup(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
 // descriptor pairs, so every global access is coalesced); also
 // pd_g = x_c,g . u_g, the per-block column partial sums of U, and the copies of
 // U the chosen precision needs (FP64, FP32, or split BF16 in both layouts).
-constexpr int GT = 16;
+// Small systems take 4 geometries per block so that the grid still covers the
+// GPU; large ones take 16, which keeps the column partials few.
+static int jv_group(int64_t N) { return N < 8192 ? 4 : 16; }
 
 // MODE: 0 = FP64, 1 = FP32, 2 = split BF16 (hi in U/UT, lo in Ul/UTl).
 // U is written row-major with leading dimension ldu (BF16: fragment-major
 // with K = ldu); UT (if not null) is the transposed copy with leading
 // dimension ldut (BF16: fragment-major, K = ldut).  Padding is left untouched.
-template <int MODE>
+template <int MODE, int GT>
 __global__ __launch_bounds__(256) void k_jv_tile(const double* __restrict__ R, const int* __restrict__ pairs,
                                                  const double* __restrict__ v, const double* __restrict__ Xc,
                                                  int64_t N, int M, int64_t D, void* __restrict__ U,
@@ -112,25 +114,36 @@ __global__ __launch_bounds__(256) void k_jv_tile(const double* __restrict__ R, c
   }
 }
 
-// s = sum of the per-block column partials (nblk x D): 16 columns per block;
-// the 16 lanes of a column take partials q, q + 16, ... and combine by a
-// fixed butterfly.
+
+template <int MODE, typename... A>
+static void launch_jv(int64_t N, int M, hipStream_t st, A... args) {
+  const int gt = jv_group(N);
+  const size_t shm = (size_t)2 * gt * 3 * M * sizeof(double);
+  if (gt == 4)
+    k_jv_tile<MODE, 4><<<cdiv(N, 4), 256, shm, st>>>(args...);
+  else
+    k_jv_tile<MODE, 16><<<cdiv(N, 16), 256, shm, st>>>(args...);
+}
+
+// s = sum of the per-block column partials (nblk x D): one wave per column,
+// four columns per block; lane l takes partials l, l + 64, ... and a fixed
+// butterfly combines the lanes.
 __global__ __launch_bounds__(256) void k_colsum_final(const double* __restrict__ part, int nblk, int64_t D,
                                                       double* __restrict__ s) {
-  const int64_t col = (int64_t)blockIdx.x * 16 + (threadIdx.x >> 4);
-  const int q = threadIdx.x & 15;
+  const int64_t col = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int q = threadIdx.x & 63;
   double a0 = 0.0, a1 = 0.0;
   if (col < D) {
     int i = q;
-    for (; i + 16 < nblk; i += 32) {
+    for (; i + 64 < nblk; i += 128) {
       a0 += part[(int64_t)i * D + col];
-      a1 += part[(int64_t)(i + 16) * D + col];
+      a1 += part[(int64_t)(i + 64) * D + col];
     }
     if (i < nblk) a0 += part[(int64_t)i * D + col];
   }
   double t = a0 + a1;
 #pragma unroll
-  for (int off = 8; off >= 1; off >>= 1) t += __shfl_xor(t, off);
+  for (int off = 32; off >= 1; off >>= 1) t += __shfl_xor(t, off);
   if (q == 0 && col < D) s[col] = t;
 }
 
@@ -184,6 +197,16 @@ __global__ void k_jtg(const double* __restrict__ R, const double* __restrict__ G
   jtg_atoms(sR, sG, g, M, accumulate ? nullptr : v, shift, y, accumulate != 0);
 }
 
+// Sum of the n partials p[0..n) by the calling wave: lane l adds l, l + 64,
+// ..., and a fixed butterfly combines the lanes; every lane gets the sum.
+__device__ inline double wave_sum_parts(const double* __restrict__ p, int n) {
+  double a = 0.0;
+  for (int q = threadIdx.x & 63; q < n; q += 64) a += p[q];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o);
+  return a;
+}
+
 // The split-K reduction of GEMM 2 fused with J^T G: one block per geometry
 // forms its row of G = sum_z part_z + a0 s + w Xt in LDS (the arithmetic and
 // order of k_g_reduce) and applies J^T to it; G never goes to HBM.
@@ -197,16 +220,16 @@ __global__ void k_jtg_reduce(const PT* __restrict__ part, int splits, int64_t ro
   double* sG = sm + 3 * M;
   __shared__ double wsh;
   const int64_t g = blockIdx.x;
-  if (threadIdx.x == 0) {
-    double w = 0.0;
-    for (int q = 0; q < ntn; ++q) w += wpart[g * ntn + q];
-    wsh = w;
+  if (threadIdx.x < 64) {
+    const double w = wave_sum_parts(wpart + g * ntn, ntn);
+    if (threadIdx.x == 0) wsh = w;
   }
   for (int i = threadIdx.x; i < 3 * M; i += blockDim.x) sR[i] = R[g * 3 * M + i];
   __syncthreads();
   const double w = wsh;
   for (int64_t c = threadIdx.x; c < D; c += blockDim.x) {
     double acc = 0.0;
+#pragma unroll 4
     for (int z = 0; z < splits; ++z) acc += (double)part[((int64_t)z * rows + g) * D + c];
     sG[c] = acc + a0 * s[c] + w * Xt[g * D + c];
   }
@@ -405,15 +428,15 @@ __global__ __launch_bounds__(256) void k_g_reduce(const PT* __restrict__ part, i
                                                   double* __restrict__ G) {
   __shared__ double wsh;
   const int64_t r = blockIdx.x;
-  if (threadIdx.x == 0) {
-    double w = 0.0;
-    for (int q = 0; q < ntn; ++q) w += wpart[r * ntn + q];
-    wsh = w;
+  if (threadIdx.x < 64) {
+    const double w = wave_sum_parts(wpart + r * ntn, ntn);
+    if (threadIdx.x == 0) wsh = w;
   }
   __syncthreads();
   const double w = wsh;
   for (int64_t c = threadIdx.x; c < cols; c += blockDim.x) {
     double acc = 0.0;
+#pragma unroll 4
     for (int z = 0; z < splits; ++z) acc += (double)part[((int64_t)z * rows + r) * cols + c];
     G[r * cols + c] = acc + a0 * s[c] + w * Xt[r * cols + c];
   }
@@ -622,7 +645,7 @@ static void ensure_work(ffk_system* s, int prec, hipStream_t st) {
   if (!w.pd) {
     w.pd.alloc(N * 8);
     w.s.alloc(D * 8);
-    w.spart.alloc((int64_t)cdiv(N, GT) * D * 8);
+    w.spart.alloc((int64_t)cdiv(N, jv_group(N)) * D * 8);
     w.G.alloc(N * D * 8);
     w.wpart.alloc(N * (pad_rows(N) / 64) * 8);   // one partial per GEMM 1 tile column (tiles >= 64 wide)
     w.part.alloc(part_budget(N, D));
@@ -671,25 +694,24 @@ void kernel_mvm_ev(ffk_system* s, const double* v, double* y, double shift, int 
   const int M = s->M;
   MvmWork& w = s->work;
   const int64_t Nr = pad_rows(N), ldu = rup(D, 64);
-  const int nblk = cdiv(N, GT);
-  const size_t shm = (size_t)2 * GT * 3 * M * sizeof(double);
+  const int nblk = cdiv(N, jv_group(N));
   double* pd = w.pd.as<double>();
   double* cp = w.spart.as<double>();
   clk_begin(CLK_JV, st);
   if (prec == FFK_FP64)
-    k_jv_tile<0><<<nblk, 256, shm, st>>>(s->R.as<double>(), s->pairs.as<int>(), v, s->Xc.as<double>(), N, M, D,
-                                         w.U64.get(), nullptr, ldu, w.UT64.get(), nullptr, Nr, pd, cp);
+    launch_jv<0>(N, M, st, s->R.as<double>(), s->pairs.as<int>(), v, s->Xc.as<double>(), N, M, D,
+                 w.U64.get(), nullptr, ldu, w.UT64.get(), nullptr, Nr, pd, cp);
   else if (prec == FFK_FP32)
-    k_jv_tile<1><<<nblk, 256, shm, st>>>(s->R.as<double>(), s->pairs.as<int>(), v, s->Xc.as<double>(), N, M, D,
-                                         w.U32.get(), nullptr, ldu, w.UT32.get(), nullptr, Nr, pd, cp);
+    launch_jv<1>(N, M, st, s->R.as<double>(), s->pairs.as<int>(), v, s->Xc.as<double>(), N, M, D,
+                 w.U32.get(), nullptr, ldu, w.UT32.get(), nullptr, Nr, pd, cp);
   else
-    k_jv_tile<2><<<nblk, 256, shm, st>>>(s->R.as<double>(), s->pairs.as<int>(), v, s->Xc.as<double>(), N, M, D,
-                                         w.Uh.get(), w.Ul.get(), ldu, w.UTh.get(), w.UTl.get(), Nr, pd, cp);
+    launch_jv<2>(N, M, st, s->R.as<double>(), s->pairs.as<int>(), v, s->Xc.as<double>(), N, M, D,
+                 w.Uh.get(), w.Ul.get(), ldu, w.UTh.get(), w.UTl.get(), Nr, pd, cp);
   LAUNCHCHK();
   clk_end(CLK_JV, st);
   mark(ev, 1, st);
   clk_begin(CLK_COLSUM, st);
-  k_colsum_final<<<cdiv(D, 16), 256, 0, st>>>(cp, nblk, D, w.s.as<double>());
+  k_colsum_final<<<cdiv(D, 4), 256, 0, st>>>(cp, nblk, D, w.s.as<double>());
   LAUNCHCHK();
   clk_end(CLK_COLSUM, st);
   mark(ev, 2, st);
@@ -798,7 +820,7 @@ void rect_mvm(const ffk_system* tr, const ffk_system* te, const double* alpha, d
   require(tr->sigma == te->sigma, "kernel product: sigma differs");
   const int64_t Ns = tr->N, Nt = te->N, D = tr->D;
   const int M = tr->M;
-  const int nblk = cdiv(Ns, GT);
+  const int nblk = cdiv(Ns, jv_group(Ns));
   const int ntn = cdiv(Ns, 128);
   RectCache local;
   RectCache& c = cache ? *cache : local;
@@ -830,11 +852,10 @@ void rect_mvm(const ffk_system* tr, const ffk_system* te, const double* alpha, d
     LAUNCHCHK();
     if (cache) c.tgt = te;
   }
-  k_jv_tile<0><<<nblk, 256, (size_t)2 * GT * 3 * M * sizeof(double), st>>>(
-      tr->R.as<double>(), tr->pairs.as<int>(), alpha, tr->Xc.as<double>(), Ns, M, D, c.U.get(), nullptr, D, nullptr,
-      nullptr, 0, c.pd.as<double>(), c.cpart.as<double>());
+  launch_jv<0>(Ns, M, st, tr->R.as<double>(), tr->pairs.as<int>(), alpha, tr->Xc.as<double>(), Ns, M, D, c.U.get(),
+               nullptr, D, nullptr, nullptr, (int64_t)0, c.pd.as<double>(), c.cpart.as<double>());
   LAUNCHCHK();
-  k_colsum_final<<<cdiv(D, 16), 256, 0, st>>>(c.cpart.as<double>(), nblk, D, c.sv.as<double>());
+  k_colsum_final<<<cdiv(D, 4), 256, 0, st>>>(c.cpart.as<double>(), nblk, D, c.sv.as<double>());
   LAUNCHCHK();
   MvmArgs a{Nt, Ns, D, tr->a0, c.Xt.as<double>(), c.pd.as<double>(), c.sv.as<double>(), c.wpart.as<double>(),
             c.G.as<double>(), c.part.get(), c.part.bytes()};
