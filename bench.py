@@ -70,6 +70,28 @@ def kernel_model(name: str, N: int, D: int, n: int, k: int, L_bytes: int):
     }.get(name)
 
 
+def iteration_roofline(cfg, n: int, k: int, rec: dict, L_bytes: int = 4) -> dict:
+    """The timed mixed solve's PCG phase against a lower bound made from the peaks.
+
+    Every iteration: two passes over the stored L and about 13 passes over
+    FP64 n-vectors at the HBM peak.  Every product: the larger of its MFMA
+    time (FP64: F at the FP64 peak; split BF16: its three products at the
+    BF16 peak) and its HBM time (four N x N passes: dA, B, W written, W read;
+    32 B per entry in FP64, 16 B in split BF16).  FP64 products are the ones
+    before the switch plus one per refresh; the rest are split BF16."""
+    N, D = cfg.N, cfg.D
+    F = mvm_flops(N, D)
+    t_apply = (2.0 * L_bytes * n * k + 13 * 8.0 * n) / (PEAK_HBM_GBS * 1e9)
+    t64 = max(F / (PEAK_TFLOPS["fp64"] * 1e12), 32.0 * N * N / (PEAK_HBM_GBS * 1e9))
+    tx3 = max(3.0 * F / (PEAK_TFLOPS["bf16"] * 1e12), 16.0 * N * N / (PEAK_HBM_GBS * 1e9))
+    it, sw, nr = rec["iters"], rec["switch_iter"], rec["n_refresh"]
+    ideal = it * t_apply + (sw + nr) * t64 + (it - sw) * tx3
+    return {"ideal_pcg_s": ideal, "measured_pcg_s": rec["t_pcg_s"], "frac": ideal / rec["t_pcg_s"],
+            "ideal_us_per_iteration": 1e6 * ideal / it, "measured_us_per_iteration": 1e6 * rec["t_pcg_s"] / it,
+            "ideal_apply_us": 1e6 * t_apply, "ideal_fp64_product_us": 1e6 * t64,
+            "ideal_bf16x3_product_us": 1e6 * tx3, "fp64_products": sw + nr, "bf16x3_products": it - sw}
+
+
 def time_mvm(ffk, ctx, S, v, prec, steps, warmup):
     import torch
     for _ in range(warmup):
@@ -407,6 +429,7 @@ def main(argv=None) -> int:
         "learned_setup": setup,
         "converged": ok_all,
         "roofline": roof,
+        "iteration_roofline": iteration_roofline(cfg, n, keff, recs[-1]),
         "kernel_clocks_ms": clock_ms,
         "solves": arms,
         "speedup_vs_fp64": (arms["fp64"]["t_total_s"] / sec) if "fp64" in arms else None,
