@@ -3,7 +3,7 @@ checked against the FP64 oracle on sampled target geometries.
 
 The oracle evaluates the product one target geometry at a time
 (y_i = sum_j J_i^T H_ij J_j v_j), so a handful of rows of the
-n = 630000 and n = 3.6M products is cheap; the first, last and middle
+n = 126000 to 3.6M products is cheap; the first, last and middle
 geometries and a seeded random set are compared.  Tolerances are norm-wise
 relative errors over the sampled rows: FP64 products agree to rounding, the
 FP32 and split-BF16 products (FP32 accumulation over K = 2N terms) to a few
@@ -38,7 +38,7 @@ def sample_targets(N, seed=0, extra=4):
     return np.unique(np.concatenate([[0, 1, N // 2, N - 1], rng.integers(0, N, extra)]))
 
 
-@pytest.mark.parametrize("name", ["m42_n5000", "m60_n20000"])
+@pytest.mark.parametrize("name", ["m21_n2000", "m21_n10000", "m42_n5000", "m60_n20000"])
 def test_full_size_products_match_oracle_rows(ffk, ctx, name):
     cfg = synth.CONFIGS[name]
     s = synth.config_system(cfg)
@@ -55,3 +55,33 @@ def test_full_size_products_match_oracle_rows(ffk, ctx, name):
         err = np.linalg.norm(y - ref) / np.linalg.norm(ref)
         print("  relerr", prec, err, flush=True)
         assert err <= TOL[prec]
+
+
+def test_workload_solve_true_residual_m21_n2000(ffk, ctx):
+    """The timed solve at its full size and in its launch configuration:
+    M=21, N=2000, lambda=1e-9, k=2000 columns, FP32 L, FP64 products until
+    the recursive residual falls below the switch fraction of |F|, split BF16
+    after, FP64 true-residual refreshes.  Uniform selection stands in for the
+    trained network (which only chooses the columns).  The oracle's own FP64
+    product over all 2000 geometries gives the true residual of the returned
+    alpha; it must meet the 1e-6 bound and agree with the residual the
+    library reports."""
+    cfg = synth.CONFIGS["m21_n2000"]
+    s = synth.config_system(cfg)
+    print("workload solve", cfg.name, flush=True)
+    S = ffk.descriptor_build(ctx, torch.as_tensor(s.R, device="cuda"), cfg.sigma)
+    F = s.flat_forces()
+    idx = ffk.nystrom_select(ctx, S, "uniform", cfg.k, lam=cfg.lam, seed=cfg.sel_seed)
+    P = ffk.precond_build(ctx, S, idx, cfg.lam, store=ffk.FP32)
+    alpha, rep = ffk.pcg_solve(ctx, S, P, torch.as_tensor(F, device="cuda"), cfg.lam, tol=1e-6, max_iter=50000,
+                               prec=ffk.BF16X3, refresh_every=ffk.MIXED_REFRESH, escalate=True,
+                               switch_below=ffk.MIXED_SWITCH_BELOW)
+    print("  iterations %d, switch %d, refreshes %d, reported residual %.3e"
+          % (rep.iters, rep.switch_iter, rep.n_refresh, rep.rel_res_true), flush=True)
+    assert rep.status == 0
+    a = alpha.cpu().numpy()
+    res = F - (ok.kernel_mvm(s.R, s.R, a, cfg.sigma) + cfg.lam * a)
+    rel = np.linalg.norm(res) / np.linalg.norm(F)
+    print("  oracle true residual %.6e" % rel, flush=True)
+    assert rel <= 1e-6
+    assert abs(rel - rep.rel_res_true) <= 1e-9
