@@ -75,21 +75,26 @@ def iteration_roofline(cfg, n: int, k: int, rec: dict, L_bytes: int = 4) -> dict
 
     Every iteration: two passes over the stored L and about 13 passes over
     FP64 n-vectors at the HBM peak.  Every product: the larger of its MFMA
-    time (FP64: F at the FP64 peak; split BF16: its three products at the
-    BF16 peak) and its HBM time (four N x N passes: dA, B, W written, W read;
-    32 B per entry in FP64, 16 B in split BF16).  FP64 products are the ones
-    before the switch plus one per refresh; the rest are split BF16."""
+    time (F at the peak of its precision; split BF16: its three products at
+    the BF16 peak) and its HBM time (four N x N passes: dA, B, W written, W
+    read; 32 B per entry in FP64, 16 B in FP32 and split BF16).  Products
+    before the switch run in the first-phase precision, refreshes in FP64,
+    the rest in split BF16."""
     N, D = cfg.N, cfg.D
     F = mvm_flops(N, D)
-    t_apply = (2.0 * L_bytes * n * k + 13 * 8.0 * n) / (PEAK_HBM_GBS * 1e9)
-    t64 = max(F / (PEAK_TFLOPS["fp64"] * 1e12), 32.0 * N * N / (PEAK_HBM_GBS * 1e9))
-    tx3 = max(3.0 * F / (PEAK_TFLOPS["bf16"] * 1e12), 16.0 * N * N / (PEAK_HBM_GBS * 1e9))
+    hbm = PEAK_HBM_GBS * 1e9
+    t_apply = (2.0 * L_bytes * n * k + 13 * 8.0 * n) / hbm
+    t64 = max(F / (PEAK_TFLOPS["fp64"] * 1e12), 32.0 * N * N / hbm)
+    t32 = max(F / (PEAK_TFLOPS["fp32"] * 1e12), 16.0 * N * N / hbm)
+    tx3 = max(3.0 * F / (PEAK_TFLOPS["bf16"] * 1e12), 16.0 * N * N / hbm)
     it, sw, nr = rec["iters"], rec["switch_iter"], rec["n_refresh"]
-    ideal = it * t_apply + (sw + nr) * t64 + (it - sw) * tx3
+    t_first = t32 if rec["switch_from"] == "fp32" else t64
+    ideal = it * t_apply + sw * t_first + nr * t64 + (it - sw) * tx3
     return {"ideal_pcg_s": ideal, "measured_pcg_s": rec["t_pcg_s"], "frac": ideal / rec["t_pcg_s"],
             "ideal_us_per_iteration": 1e6 * ideal / it, "measured_us_per_iteration": 1e6 * rec["t_pcg_s"] / it,
-            "ideal_apply_us": 1e6 * t_apply, "ideal_fp64_product_us": 1e6 * t64,
-            "ideal_bf16x3_product_us": 1e6 * tx3, "fp64_products": sw + nr, "bf16x3_products": it - sw}
+            "ideal_apply_us": 1e6 * t_apply, "ideal_product_us": {"fp64": 1e6 * t64, "fp32": 1e6 * t32,
+                                                                  "bf16x3": 1e6 * tx3},
+            "products": {"first_phase_" + rec["switch_from"]: sw, "fp64_refresh": nr, "bf16x3": it - sw}}
 
 
 def time_mvm(ffk, ctx, S, v, prec, steps, warmup):
@@ -146,14 +151,14 @@ def solve(ffk, ctx, R, F, cfg, arm: str, net=None):
         torch.cuda.synchronize()
         t2 = time.perf_counter()
     prec = {"fp64": ffk.FP64, "mixed": ffk.BF16X3, "mixed_pivchol": ffk.BF16X3, "mixed_fp32": ffk.FP32}[arm]
-    SWITCH_BELOW, REFRESH = ffk.MIXED_SWITCH_BELOW, ffk.MIXED_REFRESH
+    SWITCH_BELOW, REFRESH, FROM = ffk.MIXED_SWITCH_BELOW, ffk.MIXED_REFRESH, ffk.MIXED_SWITCH_FROM
     alpha, rep = ffk.pcg_solve(ctx, S, P, F, cfg.lam, tol=TOL, max_iter=50000, prec=prec, refresh_every=REFRESH,
-                               escalate=True, switch_below=SWITCH_BELOW if mixed else 0.0)
+                               escalate=True, switch_below=SWITCH_BELOW if mixed else 0.0, switch_from=FROM)
     torch.cuda.synchronize()
     t3 = time.perf_counter()
-    sched = "fp64 until |r| < %g |F|, then %s; fp64 refresh every %d"
+    sched = ("fp64" if FROM == ffk.FP64 else "fp32") + " until |r| < %g |F|, then %s; fp64 refresh every %d"
     rec = {
-        "arm": arm, "selection": how,
+        "arm": arm, "selection": how, "switch_from": ("fp64" if FROM == ffk.FP64 else "fp32") if mixed else None,
         "products": {"fp64": "fp64", "mixed": sched % (SWITCH_BELOW, "bf16x3", REFRESH),
                      "mixed_pivchol": sched % (SWITCH_BELOW, "bf16x3", REFRESH),
                      "mixed_fp32": sched % (SWITCH_BELOW, "fp32", REFRESH)}[arm],

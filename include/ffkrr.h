@@ -231,15 +231,19 @@ typedef struct {
   int32_t prec;           /* ffk_precision of the MVM inside the iteration */
   int32_t refresh_every;  /* recompute r = F - K_lambda alpha in FP64 every so many
                              iterations (<= 0: never, except at convergence) */
-  int32_t escalate;       /* 1: move to a more accurate MVM precision when a
-                             refresh shows no progress (BF16 -> BF16X3 -> FP32 -> FP64) */
+  int32_t escalate;       /* 1: move to a more accurate MVM precision (BF16 -> BF16X3 ->
+                             FP32 -> FP64) when a refresh finds the true residual off the
+                             recursive one by more than half of itself, no new best true
+                             residual for 100 refreshes, or divergence (10x the best; then
+                             the solve restarts from the best iterate) */
   int32_t flexible;       /* 1: Polak-Ribiere beta (robust to inexact operators) */
   int32_t timing;         /* 1: time MVM / preconditioner / vector phases with events */
-  double switch_below;    /* > 0: FP64 products while the updated residual is above
-                             switch_below |F|, then `prec` (0: `prec` from the start) */
+  double switch_below;    /* > 0: `switch_from` products while the updated residual is
+                             above switch_below |F|, then `prec` (0: `prec` from the start) */
   int32_t progress_every; /* > 0: print one line to stderr every so many iterations
                              (iteration, updated and true residual, precision) */
-  int32_t reserved;       /* 0 */
+  int32_t switch_from;    /* precision of the products before the switch: FFK_FP64 (0,
+                             the default) or FFK_FP32; anything else is FFK_ERR_ARG */
 } ffk_pcg_opts;
 
 typedef struct {
@@ -250,7 +254,7 @@ typedef struct {
   double rel_res_updated; /* final recursively updated residual / |F| */
   int32_t final_prec;     /* precision in use at the end */
   int32_t status;         /* same as the return value */
-  int64_t switch_iter;    /* iteration at which the products left FP64 (-1: never) */
+  int64_t switch_iter;    /* iteration at which the products left `switch_from` (-1: never) */
   int64_t esc_iter[3];    /* iterations at which escalations happened (-1: none) */
   double t_mvm_ms, t_prec_ms, t_vec_ms, t_refresh_ms, t_total_ms;
   double* hist_host;      /* optional caller buffer: updated residual norm / |F| per iteration */

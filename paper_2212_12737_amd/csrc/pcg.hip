@@ -9,15 +9,19 @@
 // recomputed with the FP64 product every `refresh_every` iterations and
 // replaces the recursively updated one (residual replacement; p is kept), and
 // convergence is only declared on an FP64 true residual.  With `escalate`,
-// a refresh that shows divergence (10x the best true residual) or no
-// improvement for 30 refreshes moves the product one rung up the ladder
-// BF16 -> BF16X3 -> FP32 -> FP64 and restarts from the best iterate.
+// a refresh moves the product one rung up the ladder
+// BF16 -> BF16X3 -> FP32 -> FP64 when the true residual has drifted from the
+// recursive one by more than half of itself (the products' rounding now
+// shows) or has not improved for 100 refreshes; the direction is kept.  A
+// refresh that shows divergence (10x the best true residual) also moves up a
+// rung, and restarts from the best iterate.
 // `flexible` switches beta to Polak-Ribiere, -gamma z^T q / rho.
-// `switch_below` > 0 runs the first iterations with FP64 products and moves to
-// the reduced precision once the residual has fallen below switch_below |F|
-// (accurate products while the residual is large, cheap ones afterwards).
+// `switch_below` > 0 runs the first iterations with more accurate products
+// (`switch_from`: FP64 or FP32) and moves to the reduced precision once the
+// residual has fallen below switch_below |F| (accurate products while the
+// residual is large, cheap ones afterwards).
 // A breakdown (p^T q <= 0) under a reduced-precision product escalates like a
-// stagnating refresh when `escalate` is set.
+// diverging refresh (restart from the best iterate) when `escalate` is set.
 #include <chrono>
 #include <cstdio>
 
@@ -26,6 +30,15 @@
 namespace ffk {
 
 enum { S_RHO0 = 0, S_RHO1 = 1, S_PAP = 2, S_RR = 3, S_ZQ = 4, S_FF = 5, S_TMP = 6, NSC = 8 };
+
+// Escalation tests at a refresh (reduced-precision products only).  A true
+// residual that differs from the recursive one by more than kGapEscalate of
+// itself means the products' rounding now shows in the residual; no new best
+// true residual for kStallRefreshes refreshes means no progress at all.  Both
+// move one rung up and keep the direction.  CG's residual norm is not
+// monotone, so a plateau above an earlier best alone is not taken as a sign.
+constexpr double kGapEscalate = 0.5;
+constexpr int kStallRefreshes = 100;
 
 // x += g p, r -= g q with g = rho / p^T q, and the block partials of |r|^2 of
 // the updated r (fused_parts grid).  Every block forms p^T q itself from the
@@ -124,6 +137,8 @@ ffk_status pcg_solve(ffk_system* s, const ffk_precond* P, const double* F, doubl
   require(lam > 0.0, "pcg_solve: lambda must be > 0");
   require(o->tol > 0.0, "pcg_solve: tol must be > 0");
   require(o->prec >= FFK_FP64 && o->prec <= FFK_BF16X3, "pcg_solve: unknown precision");
+  require(o->switch_from == FFK_FP64 || o->switch_from == FFK_FP32,
+          "pcg_solve: the products before the switch must be FP64 or FP32");
   if (P) require(P->n == n, "pcg_solve: preconditioner size does not match the system");
   const int64_t max_iter = o->max_iter > 0 ? o->max_iter : n;
   const bool timing = o->timing != 0;
@@ -175,7 +190,8 @@ ffk_status pcg_solve(ffk_system* s, const ffk_precond* P, const double* F, doubl
   HIPCHK(hipMemcpyAsync(R, F, n * 8, hipMemcpyDeviceToDevice, st));
   HIPCHK(hipMemcpyAsync(best.get(), alpha, n * 8, hipMemcpyDeviceToDevice, st));
   int prec = o->prec;
-  bool hi_phase = o->switch_below > 0.0 && prec != FFK_FP64;
+  const int first = o->switch_from;
+  bool hi_phase = o->switch_below > 0.0 && prec != FFK_FP64 && prec != first;
   int64_t switch_iter = hi_phase ? -1 : 0;
   int64_t esc_iter[3] = {-1, -1, -1};
   int rho = S_RHO0;
@@ -197,6 +213,14 @@ ffk_status pcg_solve(ffk_system* s, const ffk_precond* P, const double* F, doubl
   }
   int64_t hist_len = 0;
   const int refresh = o->refresh_every;
+  // One rung up without a restart: the residual has just been replaced by the
+  // true one, and the direction is kept (a residual replacement).
+  auto step_up = [&]() {
+    if (n_esc < 3) esc_iter[n_esc] = it;
+    prec = next_rung(prec);
+    ++n_esc;
+    since_best = 0;
+  };
   auto escalate_now = [&]() {
     if (n_esc < 3) esc_iter[n_esc] = it;
     prec = next_rung(prec);
@@ -232,7 +256,7 @@ ffk_status pcg_solve(ffk_system* s, const ffk_precond* P, const double* F, doubl
   // breakdown restart or a residual replacement, the speculative direction is
   // discarded (p is only replaced after the decision).
   while (status == FFK_NOT_CONVERGED && it < max_iter) {
-    const int cur = hi_phase ? FFK_FP64 : prec;
+    const int cur = hi_phase ? first : prec;
     {
       Timer tm(timing, st, &t_mvm);
       kernel_mvm(s, Pv, Q, lam, cur, st);
@@ -273,15 +297,22 @@ ffk_status pcg_solve(ffk_system* s, const ffk_precond* P, const double* F, doubl
     if (o->progress_every > 0 && it % o->progress_every == 0) {
       static const char* names[4] = {"fp64", "fp32", "bf16", "bf16x3"};
       fprintf(stderr, "pcg it %lld  updated residual %.3e  last true residual %.3e  products %s\n", (long long)it,
-              rel_upd, rel_true, names[hi_phase ? FFK_FP64 : cur]);
+              rel_upd, rel_true, names[cur]);
       fflush(stderr);
     }
     const bool candidate = rel_upd <= o->tol;
     if (candidate || periodic) {
+      const double upd = rel_upd;   // the recursive residual the true one replaces
       const double tr = true_residual();
       ++n_ref;
       rel_true = sqrt(tr) / fnorm;
       rel_upd = rel_true;
+      const double gap = fabs(rel_true - upd) / rel_true;
+      if (o->progress_every > 0) {
+        fprintf(stderr, "pcg refresh at %lld  true %.4e  recursive %.4e  gap %.4f\n", (long long)it, rel_true, upd,
+                gap);
+        fflush(stderr);
+      }
       if (rel_true <= o->tol) {
         status = FFK_OK;
         break;
@@ -293,9 +324,12 @@ ffk_status pcg_solve(ffk_system* s, const ffk_precond* P, const double* F, doubl
       } else {
         ++since_best;
       }
-      if (o->escalate && cur != FFK_FP64 && (tr > 100.0 * best_true || since_best >= 30)) {
-        escalate_now();
-        continue;
+      if (o->escalate && cur != FFK_FP64) {
+        if (tr > 100.0 * best_true) {   // diverging: back to the best iterate
+          escalate_now();
+          continue;
+        }
+        if (gap > kGapEscalate || since_best >= kStallRefreshes) step_up();
       }
       have_next = false;   // r was replaced: the direction must come from it
     }
@@ -317,7 +351,7 @@ ffk_status pcg_solve(ffk_system* s, const ffk_precond* P, const double* F, doubl
     rep->n_escalations = n_esc;
     rep->rel_res_true = rel_true;
     rep->rel_res_updated = rel_upd;
-    rep->final_prec = hi_phase ? FFK_FP64 : prec;
+    rep->final_prec = hi_phase ? first : prec;
     rep->status = status;
     rep->switch_iter = switch_iter;
     for (int e = 0; e < 3; ++e) rep->esc_iter[e] = esc_iter[e];

@@ -35,7 +35,7 @@ class PcgOpts(ctypes.Structure):
     _fields_ = [("lam", ctypes.c_double), ("tol", ctypes.c_double), ("max_iter", ctypes.c_int64),
                 ("prec", ctypes.c_int32), ("refresh_every", ctypes.c_int32), ("escalate", ctypes.c_int32),
                 ("flexible", ctypes.c_int32), ("timing", ctypes.c_int32), ("switch_below", ctypes.c_double),
-                ("progress_every", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("progress_every", ctypes.c_int32), ("switch_from", ctypes.c_int32)]
 
 
 class PcgReport(ctypes.Structure):
@@ -336,23 +336,26 @@ class Report:
     esc_iter: tuple = ()
 
 
-# Mixed-precision schedule used by the benchmark and the studies: FP64 products
-# until the recursive residual is below MIXED_SWITCH_BELOW |F|, the reduced
-# precision afterwards, and an FP64 true-residual refresh every MIXED_REFRESH
-# iterations (measured best on the M=21, N=2000 system: switch points 0.01 ..
-# 0.95, refresh intervals 5, 10 and 20).
+# Mixed-precision schedule used by the benchmark and the studies: FP32
+# products (MIXED_SWITCH_FROM) until the recursive residual is below
+# MIXED_SWITCH_BELOW |F|, the reduced precision afterwards, and an FP64
+# true-residual refresh every MIXED_REFRESH iterations (measured best on the
+# M=21, N=2000 system: switch points 0.01 .. 0.95, refresh intervals 5, 10 and
+# 20, FP64 or FP32 before the switch; FP32 before the switch also measured
+# faster at N=10000).
 MIXED_SWITCH_BELOW = 0.7
 MIXED_REFRESH = 20
+MIXED_SWITCH_FROM = FP32
 
 
 def pcg_solve(ctx: Context, sys: System, P: Precond | None, F: torch.Tensor, lam: float, tol: float = 1e-6,
               max_iter: int = 0, prec: int = FP64, refresh_every: int = 10, escalate: bool = True,
               flexible: bool = False, timing: bool = False, hist_cap: int = 0, alpha: torch.Tensor | None = None,
-              switch_below: float = 0.0, progress_every: int = 0, stream=None):
+              switch_below: float = 0.0, progress_every: int = 0, switch_from: int = FP64, stream=None):
     if alpha is None:
         alpha = torch.empty(sys.n, dtype=torch.float64, device=ctx.torch_device)
     o = PcgOpts(lam, tol, max_iter, prec, refresh_every, int(escalate), int(flexible), int(timing), switch_below,
-                int(progress_every), 0)
+                int(progress_every), int(switch_from))
     rep = PcgReport()
     hist = (ctypes.c_double * hist_cap)() if hist_cap > 0 else None
     if hist is not None:

@@ -354,3 +354,29 @@ def test_pcg_m9_n200_mixed_precision_reaches_fp64_residual(ffk, ctx, small, prec
           flush=True)
     assert rep.status == 0
     assert oracle_relres(K, cfg.lam, host(a), F) <= 1.01e-6
+
+
+@pytest.mark.parametrize("first", ["fp64", "fp32"])
+def test_pcg_m9_n200_switch_schedule(ffk, ctx, small, first):
+    """First-phase products in FP64 or FP32 until the recursive residual is
+    below 0.7 |F|, split BF16 after: the switch happens, and the oracle's
+    residual of the result meets the bound."""
+    cfg, s, S, K, idx = small
+    P = ffk.precond_build(ctx, S, idx, cfg.lam, store=ffk.FP32)
+    F = s.flat_forces()
+    a, rep = ffk.pcg_solve(ctx, S, P, dev(F), cfg.lam, tol=1e-6, prec=ffk.BF16X3, refresh_every=20, escalate=True,
+                           switch_below=0.7, switch_from=ffk.PRECISIONS[first], max_iter=20000)
+    print("m9_n200 switch from", first, "at", rep.switch_iter, "iters", rep.iters, "esc", rep.n_escalations,
+          rep.rel_res_true, flush=True)
+    assert rep.status == 0
+    assert 0 < rep.switch_iter < rep.iters
+    assert rep.final_prec == ffk.BF16X3
+    assert oracle_relres(K, cfg.lam, host(a), F) <= 1.01e-6
+
+
+def test_pcg_rejects_reduced_first_phase(ffk, ctx, small):
+    cfg, s, S, K, idx = small
+    P = ffk.precond_build(ctx, S, idx, cfg.lam, store=ffk.FP32)
+    F = dev(s.flat_forces())
+    with pytest.raises(ffk.FfkError):
+        ffk.pcg_solve(ctx, S, P, F, cfg.lam, prec=ffk.BF16X3, switch_below=0.7, switch_from=ffk.BF16)
