@@ -12,7 +12,7 @@
 // a refresh moves the product one rung up the ladder
 // BF16 -> BF16X3 -> FP32 -> FP64 when the true residual has drifted from the
 // recursive one by more than half of itself (the products' rounding now
-// shows) or has not improved for 100 refreshes; the direction is kept.  A
+// shows) or has not improved for 3000 iterations; the direction is kept.  A
 // refresh that shows divergence (10x the best true residual) also moves up a
 // rung, and restarts from the best iterate.
 // `flexible` switches beta to Polak-Ribiere, -gamma z^T q / rho.
@@ -34,11 +34,11 @@ enum { S_RHO0 = 0, S_RHO1 = 1, S_PAP = 2, S_RR = 3, S_ZQ = 4, S_FF = 5, S_TMP = 
 // Escalation tests at a refresh (reduced-precision products only).  A true
 // residual that differs from the recursive one by more than kGapEscalate of
 // itself means the products' rounding now shows in the residual; no new best
-// true residual for kStallRefreshes refreshes means no progress at all.  Both
+// true residual for kStallIterations iterations means no progress at all.  Both
 // move one rung up and keep the direction.  CG's residual norm is not
 // monotone, so a plateau above an earlier best alone is not taken as a sign.
 constexpr double kGapEscalate = 0.5;
-constexpr int kStallRefreshes = 100;
+constexpr int64_t kStallIterations = 3000;
 
 // x += g p, r -= g q with g = rho / p^T q, and the block partials of |r|^2 of
 // the updated r (fused_parts grid).  Every block forms p^T q itself from the
@@ -204,7 +204,7 @@ ffk_status pcg_solve(ffk_system* s, const ffk_precond* P, const double* F, doubl
 
   ffk_status status = FFK_NOT_CONVERGED;
   double best_true = fnorm * fnorm;   // alpha = 0
-  int64_t since_best = 0;
+  int64_t best_it = 0;   // iteration of the best true residual so far
   double rel_upd = 1.0, rel_true = 1.0;
   int64_t it = 0, n_ref = 0, n_esc = 0;
   if (fnorm == 0.0) {
@@ -219,7 +219,7 @@ ffk_status pcg_solve(ffk_system* s, const ffk_precond* P, const double* F, doubl
     if (n_esc < 3) esc_iter[n_esc] = it;
     prec = next_rung(prec);
     ++n_esc;
-    since_best = 0;
+    best_it = it;
   };
   auto escalate_now = [&]() {
     if (n_esc < 3) esc_iter[n_esc] = it;
@@ -228,7 +228,7 @@ ffk_status pcg_solve(ffk_system* s, const ffk_precond* P, const double* F, doubl
     HIPCHK(hipMemcpyAsync(alpha, best.get(), n * 8, hipMemcpyDeviceToDevice, st));
     true_residual();
     ++n_ref;
-    since_best = 0;
+    best_it = it;
     restart_direction();
   };
   // Next direction from the current r: z = M^-1 r, rho_new = r^T z, pn = z + beta p.
@@ -319,17 +319,15 @@ ffk_status pcg_solve(ffk_system* s, const ffk_precond* P, const double* F, doubl
       }
       if (tr < best_true) {
         best_true = tr;
-        since_best = 0;
+        best_it = it;
         HIPCHK(hipMemcpyAsync(best.get(), alpha, n * 8, hipMemcpyDeviceToDevice, st));
-      } else {
-        ++since_best;
       }
       if (o->escalate && cur != FFK_FP64) {
         if (tr > 100.0 * best_true) {   // diverging: back to the best iterate
           escalate_now();
           continue;
         }
-        if (gap > kGapEscalate || since_best >= kStallRefreshes) step_up();
+        if (gap > kGapEscalate || it - best_it >= kStallIterations) step_up();
       }
       have_next = false;   // r was replaced: the direction must come from it
     }

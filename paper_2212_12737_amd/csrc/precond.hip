@@ -470,8 +470,9 @@ template <typename TA> __device__ inline uint4 load16(const TA* p) {
 constexpr int LT_COLS = 16;    // columns per block of the transposed product
 constexpr int LN_UNROLL = 16;  // loads in flight per lane in the direct product
 // columns per block of the direct product: wide, so few partial sums remain
-// (512 measured 4% faster than 256 on n = 126000, k = 2000)
-constexpr int LN_COLS = 512;
+// (on n = 126000, k = 2000: 1024 measured 2% faster than 512, 512 5% faster
+// than 256)
+constexpr int LN_COLS = 1024;
 static_assert(LN_COLS % LN_UNROLL == 0, "direct-product column tile");
 
 // Sum of v[0..C) over the 64 lanes of a wave, one column per lane group:
@@ -506,43 +507,55 @@ template <int C> __device__ inline int lt_col(int lane) {
 }
 
 // part[blockIdx.y][c] = sum over the block's rows i of A[i + c lda] x[i].
-// Block: 256 lanes x RR
-// row chunks of V rows, C columns; each lane issues all RR x C of its loads
-// before using any (RR = 2 measured fastest on the tall L).
-template <typename TA, int C, int RR>
+// Block: 256 lanes, C columns, rows [blockIdx.y rpb, +rpb) walked in chunks of
+// 256 V rows.  Loads are software-pipelined: the next chunk's C loads per
+// lane are in flight while the current chunk is multiplied, and the lanes
+// combine their sums once, at the end.
+template <typename TA, int C>
 __global__ __launch_bounds__(256) void k_lt_part(const TA* __restrict__ A, int64_t nrow, int64_t lda, int64_t ncol,
-                                                 const double* __restrict__ x, double* __restrict__ part) {
+                                                 const double* __restrict__ x, double* __restrict__ part,
+                                                 int64_t rpb) {
   constexpr int V = Vec16<TA>::V;
+  constexpr int64_t CH = 256 * V;
   __shared__ double red[4][C];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t c0 = (int64_t)blockIdx.x * C;
+  const int64_t r0 = (int64_t)blockIdx.y * rpb;
+  const int64_t r1 = r0 + rpb < nrow ? r0 + rpb : nrow;
   double acc[C];
 #pragma unroll
   for (int c = 0; c < C; ++c) acc[c] = 0.0;
-  uint4 a[RR][C];
-  double xr[RR][V];
+  uint4 a0[C], a1[C];
+  double x0[V], x1[V];
+  // i + V <= lda whenever i < nrow: i is a multiple of V and lda of 64
+  auto load = [&](int64_t base, uint4 (&a)[C], double (&xr)[V]) {
+    const int64_t i = base + (int64_t)threadIdx.x * V;
 #pragma unroll
-  for (int h = 0; h < RR; ++h) {
-    // i + V <= lda whenever i < nrow: i is a multiple of V and lda of 64
-    const int64_t i = (int64_t)blockIdx.y * (256 * RR * V) + (int64_t)(h * 256 + threadIdx.x) * V;
+    for (int e = 0; e < V; ++e) xr[e] = (i + e < r1) ? x[i + e] : 0.0;
 #pragma unroll
-    for (int e = 0; e < V; ++e) xr[h][e] = (i + e < nrow) ? x[i + e] : 0.0;
-#pragma unroll
-    for (int c = 0; c < C; ++c) {
-      const int64_t col = c0 + c;
-      a[h][c] = (i < nrow && col < ncol) ? load16(A + col * lda + i) : make_uint4(0, 0, 0, 0);
-    }
-  }
-#pragma unroll
-  for (int h = 0; h < RR; ++h) {
-    const int64_t i = (int64_t)blockIdx.y * (256 * RR * V) + (int64_t)(h * 256 + threadIdx.x) * V;
+    for (int c = 0; c < C; ++c)
+      a[c] = (i < r1 && c0 + c < ncol) ? load16(A + (c0 + c) * lda + i) : make_uint4(0, 0, 0, 0);
+  };
+  auto mul = [&](const uint4 (&a)[C], const double (&xr)[V]) {
 #pragma unroll
     for (int c = 0; c < C; ++c) {
       double v[V];
-      Vec16<TA>::expand(a[h][c], v);
+      Vec16<TA>::expand(a[c], v);
 #pragma unroll
-      for (int e = 0; e < V; ++e) acc[c] += v[e] * xr[h][e];
+      for (int e = 0; e < V; ++e) acc[c] += v[e] * xr[e];
     }
+  };
+  int64_t b0 = r0;
+  if (b0 < r1) load(b0, a0, x0);
+  while (b0 < r1) {
+    const int64_t b1 = b0 + CH;
+    if (b1 < r1) load(b1, a1, x1);
+    mul(a0, x0);
+    if (b1 >= r1) break;
+    const int64_t b2 = b1 + CH;
+    if (b2 < r1) load(b2, a0, x0);
+    mul(a1, x1);
+    b0 = b2;
   }
   wave_reduce_cols<C>(acc, lane);
   if ((lane & (64 / C - 1)) == 0) red[wave][lt_col<C>(lane)] = acc[0];
@@ -586,20 +599,33 @@ __global__ __launch_bounds__(256) void k_ln_part(const TA* __restrict__ A, int64
 #pragma unroll
   for (int e = 0; e < V; ++e) acc[e] = 0.0;
   const TA* base = A + c0 * lda + i;
-  for (int cc = 0; cc < cend; cc += LN_UNROLL) {
-    uint4 a[LN_UNROLL];
+  // software-pipelined: the next LN_UNROLL loads are in flight while the
+  // current ones are used
+  uint4 a0[LN_UNROLL], a1[LN_UNROLL];
+  auto load = [&](int cc, uint4 (&a)[LN_UNROLL]) {
 #pragma unroll
     for (int u = 0; u < LN_UNROLL; ++u)
       a[u] = (cc + u < cend) ? load16(base + (int64_t)(cc + u) * lda) : make_uint4(0, 0, 0, 0);
+  };
+  auto mul = [&](int cc, const uint4 (&a)[LN_UNROLL]) {
 #pragma unroll
     for (int u = 0; u < LN_UNROLL; ++u) {
       const double tc = ts[cc + u];   // cc + u < CB: cc < nc <= CB, a multiple of LN_UNROLL
-      const int64_t col = c0 + cc + u;
       double v[V];
       Vec16<TA>::expand(a[u], v);
 #pragma unroll
       for (int e = 0; e < V; ++e) acc[e] += v[e] * tc;
     }
+  };
+  int cc = 0;
+  load(0, a0);
+  while (cc < cend) {
+    if (cc + LN_UNROLL < cend) load(cc + LN_UNROLL, a1);
+    mul(cc, a0);
+    if (cc + LN_UNROLL >= cend) break;
+    if (cc + 2 * LN_UNROLL < cend) load(cc + 2 * LN_UNROLL, a0);
+    mul(cc + LN_UNROLL, a1);
+    cc += 2 * LN_UNROLL;
   }
   double* out = part + (int64_t)blockIdx.y * stride + i;
 #pragma unroll
@@ -658,16 +684,31 @@ __global__ __launch_bounds__(256) void k_scale_dot(const double* __restrict__ r,
   if (threadIdx.x == 0) rz_part[blockIdx.x] = s;
 }
 
-constexpr int LT_RR = 2;       // row chunks per lane of the transposed product
-template <typename TA>
-static int64_t lt_rows() { return 256 * LT_RR * Vec16<TA>::V; }   // rows per block, transposed product
 template <typename TA>
 static int64_t ln_rows() { return 256 * Vec16<TA>::V; }           // rows per block, direct product
+// Row ranges of the transposed product: about 512 blocks in all (two per CU
+// at its register use; 500 measured faster than 250, 1000 or 2000 on
+// n = 126000, k = 2000), each a whole number of 256 V-row chunks.  Returns
+// the block count along the rows; *rpb gets the rows per block.
+static int64_t lt_target(int64_t ncol) {
+  const int64_t cb = cdiv(ncol, LT_COLS);
+  return std::max<int64_t>(1, (512 + cb / 2) / cb);
+}
+template <typename TA>
+static int lt_row_blocks(int64_t nrow, int64_t ncol, int64_t* rpb) {
+  const int64_t ch = 256 * Vec16<TA>::V;
+  const int64_t nch = cdiv(nrow, ch);
+  const int64_t y = std::max<int64_t>(1, std::min(lt_target(ncol), nch));
+  *rpb = cdiv(nch, y) * ch;
+  return (int)cdiv(nrow, *rpb);   // <= y: cdiv(a, cdiv(a, y)) <= y
+}
 
-// workspace (doubles) needed by gemv_t / gemv_n for an nrow x ncol operand
+// workspace (doubles) needed by gemv_t / gemv_n for any operand of at most
+// nrow rows and ncol columns (the row-block count of the transposed product
+// is at most min(lt_target, chunks of nrow), whatever the row count)
 template <typename TA>
 static int64_t gemv_work(int64_t nrow, int64_t ncol) {
-  const int64_t wt = cdiv(nrow, lt_rows<TA>()) * ncol;
+  const int64_t wt = std::min<int64_t>(lt_target(ncol), cdiv(nrow, 256 * Vec16<TA>::V)) * ncol;
   const int64_t wn = cdiv(ncol, LN_COLS) * (cdiv(nrow, ln_rows<TA>()) * ln_rows<TA>());
   return std::max(wt, wn);
 }
@@ -675,9 +716,10 @@ static int64_t gemv_work(int64_t nrow, int64_t ncol) {
 template <typename TA>
 static void gemv_t(const TA* A, int64_t nrow, int64_t lda, int64_t ncol, const double* x, double* y, double* part,
                    hipStream_t st, int clk = -1) {
-  const int nb = cdiv(nrow, lt_rows<TA>());
+  int64_t rpb;
+  const int nb = lt_row_blocks<TA>(nrow, ncol, &rpb);
   if (clk >= 0) clk_begin(clk, st);
-  k_lt_part<TA, LT_COLS, LT_RR><<<dim3(cdiv(ncol, LT_COLS), nb), 256, 0, st>>>(A, nrow, lda, ncol, x, part);
+  k_lt_part<TA, LT_COLS><<<dim3(cdiv(ncol, LT_COLS), nb), 256, 0, st>>>(A, nrow, lda, ncol, x, part, rpb);
   LAUNCHCHK();
   if (clk >= 0) clk_end(clk, st);
   k_sum_rows<<<cdiv(ncol, 16), 256, 0, st>>>(part, nb, ncol, y);

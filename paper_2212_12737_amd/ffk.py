@@ -344,7 +344,7 @@ class Report:
 # 20, FP64 or FP32 before the switch; FP32 before the switch also measured
 # faster at N=10000).
 MIXED_SWITCH_BELOW = 0.7
-MIXED_REFRESH = 20
+MIXED_REFRESH = 10
 MIXED_SWITCH_FROM = FP32
 
 
