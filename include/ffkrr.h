@@ -232,9 +232,9 @@ typedef struct {
   int32_t refresh_every;  /* recompute r = F - K_lambda alpha in FP64 every so many
                              iterations (<= 0: never, except at convergence) */
   int32_t escalate;       /* 1: move to a more accurate MVM precision (BF16 -> BF16X3 ->
-                             FP32 -> FP64) when a refresh finds the true residual off the
-                             recursive one by more than half of itself, no new best true
-                             residual for 3000 iterations, or divergence (10x the best; then
+                             FP32 -> FP64) when a refresh finds |r_true - r| > |r_true| / 2
+                             (r the recursive residual), no new best true residual for
+                             3000 iterations, or divergence (10x the best; then
                              the solve restarts from the best iterate) */
   int32_t flexible;       /* 1: Polak-Ribiere beta (robust to inexact operators) */
   int32_t timing;         /* 1: time MVM / preconditioner / vector phases with events */

@@ -11,7 +11,7 @@
 // convergence is only declared on an FP64 true residual.  With `escalate`,
 // a refresh moves the product one rung up the ladder
 // BF16 -> BF16X3 -> FP32 -> FP64 when the true residual has drifted from the
-// recursive one by more than half of itself (the products' rounding now
+// recursive one by more than half of its norm (the products' rounding now
 // shows) or has not improved for 3000 iterations; the direction is kept.  A
 // refresh that shows divergence (10x the best true residual) also moves up a
 // rung, and restarts from the best iterate.
@@ -32,8 +32,9 @@ namespace ffk {
 enum { S_RHO0 = 0, S_RHO1 = 1, S_PAP = 2, S_RR = 3, S_ZQ = 4, S_FF = 5, S_TMP = 6, NSC = 8 };
 
 // Escalation tests at a refresh (reduced-precision products only).  A true
-// residual that differs from the recursive one by more than kGapEscalate of
-// itself means the products' rounding now shows in the residual; no new best
+// residual whose distance from the recursive one, |r_true - r|, exceeds
+// kGapEscalate |r_true| means the products' rounding now shows in the
+// residual; no new best
 // true residual for kStallIterations iterations means no progress at all.  Both
 // move one rung up and keep the direction.  CG's residual norm is not
 // monotone, so a plateau above an earlier best alone is not taken as a sign.
@@ -94,6 +95,11 @@ __global__ __launch_bounds__(256) void k_update_p(double* __restrict__ pn, const
 __global__ void k_sub(const double* __restrict__ a, const double* __restrict__ b, double* __restrict__ c, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) c[i] = a[i] - b[i];
+}
+// b = a - b
+__global__ void k_rsub(const double* __restrict__ a, double* __restrict__ b, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = a[i] - b[i];
 }
 
 static int next_rung(int prec) {
@@ -177,6 +183,25 @@ ffk_status pcg_solve(ffk_system* s, const ffk_precond* P, const double* F, doubl
     dot64(R, R, n, PART, SC + S_RR, st);
     HIPCHK(hipMemcpyAsync(hs, SC + S_RR, 8, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
+    return hs[0];
+  };
+  // At a refresh: r_true = F - K_lambda alpha (FP64) replaces the recursive r.
+  // Returns |r_true|^2, and |r_true - r|^2 in *gap2.  Z holds the difference:
+  // every refresh recomputes the next direction, and Z with it.
+  auto refresh_residual = [&](double* gap2) -> double {
+    Timer tm(timing, st, &t_ref);
+    double* T = tmp.as<double>();
+    kernel_mvm(s, alpha, T, lam, FFK_FP64, st);
+    k_rsub<<<nb, 256, 0, st>>>(F, T, n);
+    k_sub<<<nb, 256, 0, st>>>(T, R, Z, n);
+    LAUNCHCHK();
+    dot64(T, T, n, PART, SC + S_RR, st);
+    dot64(Z, Z, n, PART, SC + S_TMP, st);
+    HIPCHK(hipMemcpyAsync(R, T, n * 8, hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemcpyAsync(hs, SC + S_RR, 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(hs + 2, SC + S_TMP, 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    *gap2 = hs[2];
     return hs[0];
   };
 
@@ -303,11 +328,12 @@ ffk_status pcg_solve(ffk_system* s, const ffk_precond* P, const double* F, doubl
     const bool candidate = rel_upd <= o->tol;
     if (candidate || periodic) {
       const double upd = rel_upd;   // the recursive residual the true one replaces
-      const double tr = true_residual();
+      double gap2 = 0.0;
+      const double tr = refresh_residual(&gap2);
       ++n_ref;
       rel_true = sqrt(tr) / fnorm;
       rel_upd = rel_true;
-      const double gap = fabs(rel_true - upd) / rel_true;
+      const double gap = tr > 0.0 ? sqrt(gap2 / tr) : 0.0;   // |r_true - r| / |r_true|
       if (o->progress_every > 0) {
         fprintf(stderr, "pcg refresh at %lld  true %.4e  recursive %.4e  gap %.4f\n", (long long)it, rel_true, upd,
                 gap);
