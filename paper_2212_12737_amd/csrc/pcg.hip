@@ -42,9 +42,10 @@ constexpr double kGapEscalate = 0.5;
 constexpr int64_t kStallIterations = 3000;
 
 // x += g p, r -= g q with g = rho / p^T q, and the block partials of |r|^2 of
-// the updated r (fused_parts grid).  Every block forms p^T q itself from the
-// np_pq partials of dot64_parts (same fixed order in every block); block 0
-// stores it in sc.
+// the updated r (fused_parts grid) in rr_part[0 .. gridDim.x).  Every block
+// forms p^T q itself from the np_pq partials of dot64_parts (same fixed order
+// in every block); block 0 stores it in sc and after the partials, in
+// rr_part[gridDim.x], so that the host reads both with one copy.
 __global__ __launch_bounds__(256) void k_axpy2_rr(double* __restrict__ x, double* __restrict__ r,
                                                   const double* __restrict__ p, const double* __restrict__ q,
                                                   double* __restrict__ sc, int rho, int64_t n,
@@ -52,7 +53,10 @@ __global__ __launch_bounds__(256) void k_axpy2_rr(double* __restrict__ x, double
                                                   double* __restrict__ rr_part) {
   __shared__ double sh[256], sh_pq[256];
   const double pq = sum_parts_block(pq_part, np_pq, sh_pq);
-  if (blockIdx.x == 0 && threadIdx.x == 0) sc[S_PAP] = pq;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    sc[S_PAP] = pq;
+    rr_part[gridDim.x] = pq;
+  }
   const double g = sc[rho] / pq;
   double acc = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
@@ -150,7 +154,8 @@ ffk_status pcg_solve(ffk_system* s, const ffk_precond* P, const double* F, doubl
   const bool timing = o->timing != 0;
   double t_mvm = 0, t_prec = 0, t_vec = 0, t_ref = 0;
 
-  DBuf r(n * 8), z(n * 8), p(n * 8), p2(n * 8), q(n * 8), tmp(n * 8), best(n * 8), sc(NSC * 8), part(2 * kRedParts * 8);
+  DBuf r(n * 8), z(n * 8), p(n * 8), p2(n * 8), q(n * 8), tmp(n * 8), best(n * 8), sc(NSC * 8),
+      part((2 * kRedParts + 1) * 8);
   double* R = r.as<double>();
   double* Z = z.as<double>();
   double* Pv = p.as<double>();
@@ -158,10 +163,10 @@ ffk_status pcg_solve(ffk_system* s, const ffk_precond* P, const double* F, doubl
   double* Q = q.as<double>();
   double* SC = sc.as<double>();
   double* PART = part.as<double>();              // partials of one reduction
-  double* PART2 = PART + kRedParts;                // a second set, for |r|^2 beside p^T q
+  double* PART2 = PART + kRedParts;                // a second set: |r|^2 partials, then p^T q
   const int nb = cdiv(n, 256);
   const int np_fused = fused_parts(n);
-  s->ctx->host_scratch.ensure(64);
+  s->ctx->host_scratch.ensure((kRedParts + 8) * 8);
   double* hs = s->ctx->host_scratch.as<double>();
   struct Ev {
     hipEvent_t e = nullptr;
@@ -291,8 +296,8 @@ ffk_status pcg_solve(ffk_system* s, const ffk_precond* P, const double* F, doubl
       const int np_pq = dot64_parts(Pv, Q, n, PART, st);
       k_axpy2_rr<<<np_fused, 256, 0, st>>>(alpha, R, Pv, Q, SC, rho, n, PART, np_pq, PART2);
       LAUNCHCHK();
-      sum_parts64(PART2, np_fused, SC + S_RR, st);
-      HIPCHK(hipMemcpyAsync(hs, SC + S_PAP, 16, hipMemcpyDeviceToHost, st));
+      // the |r|^2 partials and p^T q go to the host, which sums the partials
+      HIPCHK(hipMemcpyAsync(hs, PART2, (np_fused + 1) * 8, hipMemcpyDeviceToHost, st));
       HIPCHK(hipEventRecord(done.e, st));
     }
     ++it;
@@ -304,7 +309,9 @@ ffk_status pcg_solve(ffk_system* s, const ffk_precond* P, const double* F, doubl
       have_next = true;
     }
     HIPCHK(hipEventSynchronize(done.e));
-    const double pap = hs[0], rr = hs[1];
+    double rr = 0.0;
+    for (int b = 0; b < np_fused; ++b) rr += hs[b];
+    const double pap = hs[np_fused];
     if (!(pap > 0.0) || !std::isfinite(pap) || !std::isfinite(rr)) {
       if (o->escalate && cur != FFK_FP64) {
         escalate_now();
