@@ -255,6 +255,8 @@ void ensure_lowp_descriptor(ffk_system* sys, int prec, hipStream_t st);
 
 // mvm.hip
 void kernel_mvm(ffk_system* sys, const double* v, double* y, double shift, int prec, hipStream_t st);
+int kernel_mvm_vy(ffk_system* sys, const double* v, double* y, double shift, int prec, hipStream_t st,
+                  double* vy_part);
 void kernel_mvm_phases(ffk_system* sys, const double* v, double* y, double shift, int prec, int iters,
                        double* ms, hipStream_t st);
 void kernel_predict(const ffk_system* train, const ffk_system* test, const double* alpha,

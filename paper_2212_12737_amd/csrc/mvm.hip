@@ -147,11 +147,26 @@ __global__ __launch_bounds__(256) void k_colsum_final(const double* __restrict__
   if (q == 0 && col < D) s[col] = t;
 }
 
+// Sum of x over a block of 64, 128 or 256 lanes: wave butterflies, then the
+// wave totals in order; every lane gets the sum.
+__device__ inline double block_sum_waves(double x) {
+  __shared__ double wsum[4];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+  if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = x;
+  __syncthreads();
+  double t = 0.0;
+  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += wsum[w];
+  return t;
+}
+
 // y_g = J_g^T G_g + shift v_g, one geometry per block (thread per atom).
 // y = J^T G + shift v for geometry g from its coordinates sR (3M) and its
-// row sG (D) of G, both in LDS
+// row sG (D) of G, both in LDS.  With vy_part (and v), also v_g . y_g into
+// vy_part[g]: the block partials of v^T y, which CG needs as p^T q.
 __device__ inline void jtg_atoms(const double* sR, const double* sG, int64_t g, int M, const double* v,
-                                 double shift, double* y, bool accumulate = false) {
+                                 double shift, double* y, bool accumulate = false, double* vy_part = nullptr) {
+  double vy = 0.0;
   for (int a = threadIdx.x; a < M; a += blockDim.x) {
     double ax = 0.0, ay = 0.0, az = 0.0;
     const double xa = sR[3 * a], ya = sR[3 * a + 1], za = sR[3 * a + 2];
@@ -180,13 +195,18 @@ __device__ inline void jtg_atoms(const double* sR, const double* sG, int64_t g, 
       y[o + 1] = ay;
       y[o + 2] = az;
     }
+    if (vy_part) vy += (ax * v[o] + ay * v[o + 1]) + az * v[o + 2];
+  }
+  if (vy_part) {   // uniform across the block
+    const double t = block_sum_waves(vy);
+    if (threadIdx.x == 0) vy_part[g] = t;
   }
 }
 
 // y = J^T G + shift v, or y += J^T G with accumulate (then v is unused)
 __global__ void k_jtg(const double* __restrict__ R, const double* __restrict__ G,
                       const double* __restrict__ v, double shift, int M, int64_t D,
-                      double* __restrict__ y, int accumulate = 0) {
+                      double* __restrict__ y, int accumulate = 0, double* __restrict__ vy_part = nullptr) {
   extern __shared__ double sm[];
   double* sR = sm;
   double* sG = sm + 3 * M;
@@ -194,7 +214,7 @@ __global__ void k_jtg(const double* __restrict__ R, const double* __restrict__ G
   for (int i = threadIdx.x; i < 3 * M; i += blockDim.x) sR[i] = R[g * 3 * M + i];
   for (int64_t i = threadIdx.x; i < D; i += blockDim.x) sG[i] = G[g * D + i];
   __syncthreads();
-  jtg_atoms(sR, sG, g, M, accumulate ? nullptr : v, shift, y, accumulate != 0);
+  jtg_atoms(sR, sG, g, M, accumulate ? nullptr : v, shift, y, accumulate != 0, accumulate ? nullptr : vy_part);
 }
 
 // Sum of the n partials p[0..n) by the calling wave: lane l adds l, l + 64,
@@ -214,7 +234,7 @@ template <typename PT>
 __global__ void k_jtg_reduce(const PT* __restrict__ part, int splits, int64_t rows, const double* __restrict__ s,
                              const double* __restrict__ Xt, const double* __restrict__ wpart, int ntn, double a0,
                              const double* __restrict__ R, const double* __restrict__ v, double shift, int M,
-                             int64_t D, double* __restrict__ y) {
+                             int64_t D, double* __restrict__ y, double* __restrict__ vy_part) {
   extern __shared__ double sm[];
   double* sR = sm;
   double* sG = sm + 3 * M;
@@ -234,7 +254,7 @@ __global__ void k_jtg_reduce(const PT* __restrict__ part, int splits, int64_t ro
     sG[c] = acc + a0 * s[c] + w * Xt[g * D + c];
   }
   __syncthreads();
-  jtg_atoms(sR, sG, g, M, v, shift, y);
+  jtg_atoms(sR, sG, g, M, v, shift, y, false, vy_part);
 }
 
 // ------------------------------------------------------------- epilogues ----
@@ -682,7 +702,7 @@ static void ensure_work(ffk_system* s, int prec, hipStream_t st) {
 }
 
 void kernel_mvm_ev(ffk_system* s, const double* v, double* y, double shift, int prec, hipStream_t st,
-                   hipEvent_t* ev) {
+                   hipEvent_t* ev, double* vy_part = nullptr) {
   require(prec >= FFK_FP64 && prec <= FFK_BF16X3, "kernel_mvm: unknown precision");
   if (!s->sym.empty()) {
     require(prec == FFK_FP64, "kernel_mvm: a symmetrized kernel runs its products in FP64");
@@ -758,13 +778,15 @@ void kernel_mvm_ev(ffk_system* s, const double* v, double* y, double shift, int 
   const size_t shj = (3 * M + D) * sizeof(double);
   clk_begin(CLK_JTG, st);
   if (go.splits == 1)
-    k_jtg<<<N, tb, shj, st>>>(s->R.as<double>(), w.G.as<double>(), v, shift, M, D, y);
+    k_jtg<<<N, tb, shj, st>>>(s->R.as<double>(), w.G.as<double>(), v, shift, M, D, y, 0, vy_part);
   else if (prec == FFK_FP64)
     k_jtg_reduce<double><<<N, 256, shj, st>>>(w.part.as<double>(), go.splits, N, w.s.as<double>(), s->Xc.as<double>(),
-                                             w.wpart.as<double>(), go.ntn, s->a0, s->R.as<double>(), v, shift, M, D, y);
+                                             w.wpart.as<double>(), go.ntn, s->a0, s->R.as<double>(), v, shift, M, D, y,
+                                             vy_part);
   else
     k_jtg_reduce<float><<<N, 256, shj, st>>>(w.part.as<float>(), go.splits, N, w.s.as<double>(), s->Xc.as<double>(),
-                                            w.wpart.as<double>(), go.ntn, s->a0, s->R.as<double>(), v, shift, M, D, y);
+                                            w.wpart.as<double>(), go.ntn, s->a0, s->R.as<double>(), v, shift, M, D, y,
+                                            vy_part);
   LAUNCHCHK();
   clk_end(CLK_JTG, st);
   mark(ev, 5, st);
@@ -772,6 +794,19 @@ void kernel_mvm_ev(ffk_system* s, const double* v, double* y, double shift, int 
 
 void kernel_mvm(ffk_system* s, const double* v, double* y, double shift, int prec, hipStream_t st) {
   kernel_mvm_ev(s, v, y, shift, prec, st, nullptr);
+}
+
+// The product, plus the per-geometry partials of v^T y in vy_part (N doubles),
+// summed in a fixed order by the caller.  Returns the number of partials
+// written: N, or 0 for a symmetrized system (whose product does not form them).
+int kernel_mvm_vy(ffk_system* s, const double* v, double* y, double shift, int prec, hipStream_t st,
+                  double* vy_part) {
+  if (!s->sym.empty()) {
+    kernel_mvm_ev(s, v, y, shift, prec, st, nullptr);
+    return 0;
+  }
+  kernel_mvm_ev(s, v, y, shift, prec, st, nullptr, vy_part);
+  return (int)s->N;
 }
 
 // Average time of each phase over `iters` products: [J v (+ copies, column

@@ -38,6 +38,7 @@ enum { S_RHO0 = 0, S_RHO1 = 1, S_PAP = 2, S_RR = 3, S_ZQ = 4, S_FF = 5, S_TMP = 
 // true residual for kStallIterations iterations means no progress at all.  Both
 // move one rung up and keep the direction.  CG's residual norm is not
 // monotone, so a plateau above an earlier best alone is not taken as a sign.
+constexpr int64_t kVyMaxGeometries = 4096;
 constexpr double kGapEscalate = 0.5;
 constexpr int64_t kStallIterations = 3000;
 
@@ -164,6 +165,10 @@ ffk_status pcg_solve(ffk_system* s, const ffk_precond* P, const double* F, doubl
   double* SC = sc.as<double>();
   double* PART = part.as<double>();              // partials of one reduction
   double* PART2 = PART + kRedParts;                // a second set: |r|^2 partials, then p^T q
+  // p^T q from the product's per-geometry partials when they are few enough
+  // for every block of the update to sum them; otherwise a dot-product pass
+  DBuf vy(s->N <= kVyMaxGeometries ? s->N * 8 : 0);
+  double* VY = s->N <= kVyMaxGeometries ? vy.as<double>() : nullptr;
   const int nb = cdiv(n, 256);
   const int np_fused = fused_parts(n);
   s->ctx->host_scratch.ensure((kRedParts + 8) * 8);
@@ -287,14 +292,19 @@ ffk_status pcg_solve(ffk_system* s, const ffk_precond* P, const double* F, doubl
   // discarded (p is only replaced after the decision).
   while (status == FFK_NOT_CONVERGED && it < max_iter) {
     const int cur = hi_phase ? first : prec;
+    int np_pq = 0;   // > 0: the product left p^T q as partials in VY
     {
       Timer tm(timing, st, &t_mvm);
-      kernel_mvm(s, Pv, Q, lam, cur, st);
+      np_pq = VY ? kernel_mvm_vy(s, Pv, Q, lam, cur, st, VY) : (kernel_mvm(s, Pv, Q, lam, cur, st), 0);
     }
     {
       Timer tm(timing, st, &t_vec);
-      const int np_pq = dot64_parts(Pv, Q, n, PART, st);
-      k_axpy2_rr<<<np_fused, 256, 0, st>>>(alpha, R, Pv, Q, SC, rho, n, PART, np_pq, PART2);
+      const double* pq_part = VY;
+      if (np_pq == 0) {
+        np_pq = dot64_parts(Pv, Q, n, PART, st);
+        pq_part = PART;
+      }
+      k_axpy2_rr<<<np_fused, 256, 0, st>>>(alpha, R, Pv, Q, SC, rho, n, pq_part, np_pq, PART2);
       LAUNCHCHK();
       // the |r|^2 partials and p^T q go to the host, which sums the partials
       HIPCHK(hipMemcpyAsync(hs, PART2, (np_fused + 1) * 8, hipMemcpyDeviceToHost, st));
