@@ -7,7 +7,7 @@ equilibrium geometry, and force labels of shape (N, M, 3) flattened in the
 (geometry, atom, xyz) order the paper uses when it reshapes an n-vector into
 (n_train, d, 3) (appendix "Technical details", atomic contribution).
 
-Recipe (documented in the design doc as the input recipe):
+Recipe:
   * equilibrium geometry: a random tree; atom p bonds to a uniformly chosen
     earlier atom at a distance drawn from U[1.0, 1.5] Angstrom in a uniformly
     random direction; a placement is redrawn while any non-bonded distance is
