@@ -42,3 +42,10 @@ def test_iteration_roofline_by_hand(first):
     assert out["products"] == {"first_phase_" + first: 200, "fp64_refresh": 100, "bf16x3": 800}
     # at this size the products are MFMA-bound in FP64, N x N-traffic-bound in split BF16
     assert t64 == F / 78.6e12 and tx3 == 16 * cfg.N ** 2 / hbm
+
+
+def test_more_than_one_gpu_is_refused_before_any_gpu_work(capsys):
+    # one GPU only: the bench exits with status 2 and says why, before it
+    # imports torch or touches a device
+    assert bench.main(["--gpus", "2"]) == 2
+    assert "one GPU only" in capsys.readouterr().err
