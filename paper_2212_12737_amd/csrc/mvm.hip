@@ -655,7 +655,10 @@ static GemmOut mvm_gemms_for(const MvmArgs& a, int64_t Nr, int64_t Dk, int64_t D
   } else if constexpr (X3) {
     return mvm_gemms_dma<T, X3, CT, TileLX3, TileLX3>(a, Nr, Dk, Dr, o, st, ev);
   } else if constexpr (sizeof(T) == 2) {
-    return mvm_gemms_dma<T, X3, CT, TileL, TileL>(a, Nr, Dk, Dr, o, st, ev);
+    // GEMM 1 at 256 x 128 x 3 stages: 72 KB of LDS, so two workgroups share a
+    // CU and one's W epilogue overlaps the other's main loop (N = 20000:
+    // 2.02 -> 1.66 ms against 256 x 256, which fills a CU alone)
+    return mvm_gemms_dma<T, X3, CT, TileLX3, TileL>(a, Nr, Dk, Dr, o, st, ev);
   } else {
     // FP32 / FP64: MFMA-bound already at 128 x 128 (measured faster than the large tiles)
     return mvm_gemms_dma<T, X3, CT, TileS, TileS>(a, Nr, Dk, Dr, o, st, ev);
