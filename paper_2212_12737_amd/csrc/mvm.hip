@@ -631,15 +631,17 @@ static GemmOut mvm_gemms_dma(const MvmArgs& a, int64_t Nr, int64_t Dk, int64_t D
   return GemmOut{splits, ntn};
 }
 
-// Tile shapes: 64 x 64 (GEMM 1) and 128 x 128 (GEMM 2; BF16: 64 x 256) by 4
-// waves for small N, where the grid would otherwise leave CUs idle.  For large N the BF16
-// GEMMs are bound by operand traffic into LDS, so larger tiles by 8 waves
-// cut the bytes per flop (the split-BF16 wave sub-tile stays 64 x 64 to fit
-// the registers); FP32 and FP64 stay at 128 x 128, which measured faster.
+// Tile shapes.  Small N: 64 x 64 (GEMM 1) and 128 x 128 (GEMM 2; BF16: 64 x
+// 256) by 4 waves, where the grid would otherwise leave CUs idle.  Large N:
+// the BF16 GEMMs (single and split) use 256 x 128 by 8 waves of 64 x 64 with
+// three stages; without the lo operands that is 72 KB of LDS, so two
+// workgroups share a CU and one's epilogue overlaps the other's main loop
+// (single BF16 at N = 20000: GEMM 1 2.02 -> 1.66 ms, GEMM 2 2.89 -> 2.46 ms
+// against 256 x 256 by 8 waves, which fills a CU alone).  FP32 and FP64 stay
+// at 128 x 128, which measured faster.
 typedef DmaTile<64, 64, 2, 2, 4> TileM;        // GEMM 1 of small N: 4x more workgroups
 typedef DmaTile<128, 128, 2, 2, 4> TileS;
-typedef DmaTile<256, 256, 2, 4, 4> TileL;      // 128 x 64 per wave
-typedef DmaTile<256, 128, 4, 2, 3> TileLX3;    // 64 x 64 per wave, hi/lo operands
+typedef DmaTile<256, 128, 4, 2, 3> TileL;      // BF16 and split BF16, large N
 typedef DmaTile<64, 256, 1, 4, 3> TileW2;      // GEMM 2 of small N: one tile spans D <= 256 columns
 constexpr int64_t kLargeN = 4096;
 
@@ -652,13 +654,8 @@ static GemmOut mvm_gemms_for(const MvmArgs& a, int64_t Nr, int64_t Dk, int64_t D
     // FP64 measured 2% slower with it
     if constexpr (sizeof(T) == 2) return mvm_gemms_dma<T, X3, CT, TileM, TileW2>(a, Nr, Dk, Dr, o, st, ev);
     return mvm_gemms_dma<T, X3, CT, TileM, TileS>(a, Nr, Dk, Dr, o, st, ev);
-  } else if constexpr (X3) {
-    return mvm_gemms_dma<T, X3, CT, TileLX3, TileLX3>(a, Nr, Dk, Dr, o, st, ev);
   } else if constexpr (sizeof(T) == 2) {
-    // GEMM 1 at 256 x 128 x 3 stages: 72 KB of LDS, so two workgroups share a
-    // CU and one's W epilogue overlaps the other's main loop (N = 20000:
-    // 2.02 -> 1.66 ms against 256 x 256, which fills a CU alone)
-    return mvm_gemms_dma<T, X3, CT, TileLX3, TileL>(a, Nr, Dk, Dr, o, st, ev);
+    return mvm_gemms_dma<T, X3, CT, TileL, TileL>(a, Nr, Dk, Dr, o, st, ev);
   } else {
     // FP32 / FP64: MFMA-bound already at 128 x 128 (measured faster than the large tiles)
     return mvm_gemms_dma<T, X3, CT, TileS, TileS>(a, Nr, Dk, Dr, o, st, ev);
