@@ -380,3 +380,27 @@ def test_pcg_rejects_reduced_first_phase(ffk, ctx, small):
     F = dev(s.flat_forces())
     with pytest.raises(ffk.FfkError):
         ffk.pcg_solve(ctx, S, P, F, cfg.lam, prec=ffk.BF16X3, switch_below=0.7, switch_from=ffk.BF16)
+
+
+def test_pcg_options_flexible_timing_history_progress(ffk, ctx, small, capfd):
+    """The solve's optional outputs: Polak-Ribiere beta (flexible) reaches the
+    oracle's bound; phase timing changes nothing but the clocks (it only adds
+    events and waits); the residual history has one entry per iteration and
+    reaches the tolerance; progress lines go to stderr."""
+    cfg, s, S, K, idx = small
+    P = ffk.precond_build(ctx, S, idx, cfg.lam, store=ffk.FP32)
+    F = s.flat_forces()
+    kw = dict(tol=1e-6, prec=ffk.BF16X3, refresh_every=10, escalate=True, max_iter=20000)
+    a, rep = ffk.pcg_solve(ctx, S, P, dev(F), cfg.lam, flexible=True, **kw)
+    print("m9_n200 flexible iters", rep.iters, rep.rel_res_true, flush=True)
+    assert rep.status == 0
+    assert oracle_relres(K, cfg.lam, host(a), F) <= 1.01e-6
+    a0, r0 = ffk.pcg_solve(ctx, S, P, dev(F), cfg.lam, hist_cap=50000, progress_every=100, **kw)
+    a1, r1 = ffk.pcg_solve(ctx, S, P, dev(F), cfg.lam, timing=True, **kw)
+    assert (r1.iters, r1.rel_res_true) == (r0.iters, r0.rel_res_true)
+    assert torch.equal(a0, a1)
+    assert min(r1.t_mvm_ms, r1.t_prec_ms, r1.t_vec_ms) > 0.0 and r1.t_total_ms > 0.0
+    h = np.array(r0.hist)
+    assert len(h) == r0.iters and np.all(h > 0) and h.min() <= 1e-6
+    err = capfd.readouterr().err
+    assert err.count("pcg it ") == r0.iters // 100
