@@ -404,3 +404,15 @@ def test_pcg_options_flexible_timing_history_progress(ffk, ctx, small, capfd):
     assert len(h) == r0.iters and np.all(h > 0) and h.min() <= 1e-6
     err = capfd.readouterr().err
     assert err.count("pcg it ") == r0.iters // 100
+
+
+def test_product_phase_clocks(ffk, ctx):
+    """kernel_mvm_phases: five positive phase times per product (J v, column
+    sums, GEMM 1 with its epilogue, GEMM 2, J^T G) in every precision."""
+    s = system(7, 300, 500)
+    S = ffk.descriptor_build(ctx, dev(s.R), SIGMA)
+    v = dev(synth.random_vectors(S.n, 9))
+    for prec in ("fp64", "fp32", "bf16x3", "bf16"):
+        ph = ffk.kernel_mvm_phases(ctx, S, v, prec=ffk.PRECISIONS[prec], iters=3)
+        print("phases", prec, {k: round(t, 4) for k, t in ph.items()}, flush=True)
+        assert len(ph) == 5 and all(np.isfinite(t) and t > 0.0 for t in ph.values())

@@ -100,3 +100,23 @@ def test_training_reduces_loss_and_scores_follow_network(ffk, ctx):
     np.testing.assert_allclose(np.log(sc), o32, atol=0.05 * max(1.0, np.abs(o32).max()))
     idx = learned.select(ctx, net, S, 50, seed=3).cpu().numpy()
     assert len(idx) == 50 and len(set(idx.tolist())) == 50 and idx.min() >= 0 and idx.max() < S.n
+
+
+def test_input_standardisation(ffk, ctx):
+    """The network's inputs: raw descriptor rows as floats; fit_norm sets the
+    column mean and inverse (population) standard deviation of given rows;
+    set_norm installs any mean and inverse standard deviation."""
+    s = synth.make_system(6, 120, 0.05, True, 81, 82, 83)
+    S = ffk.descriptor_build(ctx, torch.as_tensor(s.R, device="cuda"), 10.0)
+    net = ffk.mlp_create(ctx, S.D, 64, 5)
+    raw = ffk.mlp_prepare_inputs(ctx, net, S, standardize=False).cpu().numpy()
+    np.testing.assert_allclose(raw, ok.descriptor(s.R), rtol=1e-6)
+    ffk.mlp_fit_norm(ctx, net, f32(raw))
+    Xs = ffk.mlp_prepare_inputs(ctx, net, S, standardize=True).cpu().numpy()
+    r64 = raw.astype(np.float64)
+    np.testing.assert_allclose(Xs, (r64 - r64.mean(0)) / r64.std(0), rtol=1e-4, atol=2e-4)
+    rng = np.random.default_rng(4)
+    mean, istd = rng.normal(size=S.D), rng.uniform(0.5, 2.0, S.D)
+    ffk.mlp_set_norm(ctx, net, f32(mean), f32(istd))
+    Xs2 = ffk.mlp_prepare_inputs(ctx, net, S, standardize=True).cpu().numpy()
+    np.testing.assert_allclose(Xs2, (r64 - mean.astype(np.float32)) * istd.astype(np.float32), rtol=1e-5, atol=1e-5)
