@@ -423,7 +423,7 @@ def main(argv=None) -> int:
         "value": sec, "unit": "s per solve to 1e-6 true relative residual (mixed precision)",
         "n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "ms_per_step": sec * 1e3,
         "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
-        "dtype": "bf16x3+fp64", "data": "synthetic",
+        "dtype": ("fp32" if ffk.MIXED_SWITCH_FROM == ffk.FP32 else "fp64") + "+bf16x3+fp64", "data": "synthetic",
         "config": {"workload": "%s: M=%d atoms, N=%d geometries, n=%d unknowns, D=%d, lambda=%g, k=%d Nystroem, "
                                "full solve (descriptor, %s selection, preconditioner build, mixed PCG to 1e-6)"
                                % (cfg.name, cfg.M, cfg.N, n, cfg.D, cfg.lam, cfg.k,
