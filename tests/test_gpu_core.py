@@ -416,3 +416,27 @@ def test_product_phase_clocks(ffk, ctx):
         ph = ffk.kernel_mvm_phases(ctx, S, v, prec=ffk.PRECISIONS[prec], iters=3)
         print("phases", prec, {k: round(t, 4) for k, t in ph.items()}, flush=True)
         assert len(ph) == 5 and all(np.isfinite(t) and t > 0.0 for t in ph.values())
+
+
+def test_full_rank_nystrom_preconditioner_solves_at_once(ffk, ctx):
+    """Every numerically independent column (pivoted Cholesky asked for k = n
+    stops at the rank, n - 6N): the factor reproduces K, so P = K + lambda I
+    and PCG converges in a couple of iterations to the exact (Cholesky)
+    solution."""
+    s = system(5, 20, 305)
+    S = ffk.descriptor_build(ctx, dev(s.R), SIGMA)
+    K = ok.dense_kernel(s.R, SIGMA)
+    lam = 1e-3 * np.abs(np.diag(K)).max()
+    idx = ffk.nystrom_select(ctx, S, "pivchol", S.n)
+    P = ffk.precond_build(ctx, S, idx, lam, store=ffk.FP64)
+    L = host(ffk.precond_export(ctx, P, S.n))
+    err = np.abs(L @ L.T - K).max() / np.abs(K).max()
+    print("full-rank Nystrom: k_eff", P.k_eff, "of n", S.n, "|LL^T - K| / |K|", err, flush=True)
+    assert P.k_eff == S.n - 6 * S.N
+    assert err <= 1e-9
+    F = s.flat_forces()
+    a, rep = ffk.pcg_solve(ctx, S, P, dev(F), lam, tol=1e-10, prec=ffk.FP64, max_iter=50)
+    print("  iterations", rep.iters, "residual", rep.rel_res_true, flush=True)
+    assert rep.status == 0 and rep.iters <= 3
+    ref = osv.cholesky_solve(K, lam, F)
+    assert np.linalg.norm(host(a) - ref) <= 1e-8 * np.linalg.norm(ref)
