@@ -85,3 +85,36 @@ def test_workload_solve_true_residual_m21_n2000(ffk, ctx):
     print("  oracle true residual %.6e" % rel, flush=True)
     assert rel <= 1e-6
     assert abs(rel - rep.rel_res_true) <= 1e-9
+
+
+@pytest.mark.parametrize("name", ["m21_n2000", "m21_n10000", "m42_n5000", "m60_n20000"])
+def test_full_size_product_symmetry_and_rigid_null_space(ffk, ctx, name):
+    """Properties that hold at any size, checked on the whole full-size
+    product: K is symmetric (u^T K v = v^T K u), and rigid motions of each
+    geometry are in its null space (the descriptor does not see them, so
+    J t = 0: exactly for translations, to rounding for rotations)."""
+    cfg = synth.CONFIGS[name]
+    s = synth.config_system(cfg)
+    print("full-size symmetry and null space", name, flush=True)
+    S = ffk.descriptor_build(ctx, torch.as_tensor(s.R, device="cuda"), cfg.sigma)
+    u = torch.as_tensor(synth.random_vectors(S.n, 31), device="cuda")
+    v = torch.as_tensor(synth.random_vectors(S.n, 32), device="cuda")
+    Ku = ffk.kernel_mvm(ctx, S, u)
+    Kv = ffk.kernel_mvm(ctx, S, v)
+    a, b = torch.dot(u, Kv).item(), torch.dot(v, Ku).item()
+    scale = (torch.linalg.norm(u) * torch.linalg.norm(Kv)).item()
+    print("  u^T K v %.6e  v^T K u %.6e" % (a, b), flush=True)
+    assert abs(a - b) <= 1e-12 * scale
+    rng = np.random.default_rng(33)
+    w = rng.normal(size=(cfg.N, 1, 1))
+    trans = np.broadcast_to(w * np.array([0.3, -1.0, 0.7]), s.R.shape).reshape(-1).copy()
+    omega = rng.normal(size=(cfg.N, 1, 3))
+    rot = np.cross(np.broadcast_to(omega, s.R.shape), s.R).reshape(-1)
+    norm_K = torch.linalg.norm(Kv).item() / torch.linalg.norm(v).item()
+    for prec in ("fp64", "bf16x3"):
+        yt = ffk.kernel_mvm(ctx, S, torch.as_tensor(trans, device="cuda"), prec=ffk.PRECISIONS[prec])
+        assert torch.count_nonzero(yt).item() == 0
+        yr = ffk.kernel_mvm(ctx, S, torch.as_tensor(rot, device="cuda"), prec=ffk.PRECISIONS[prec])
+        rel = torch.linalg.norm(yr).item() / (norm_K * np.linalg.norm(rot))
+        print("  %s: |K rot| / (|K| |rot|) = %.2e" % (prec, rel), flush=True)
+        assert rel <= (1e-12 if prec == "fp64" else 1e-6)
