@@ -70,3 +70,14 @@ def test_calibrated_rule_of_thumb_matches_brute_force():
         assert got == want or abs(f(got) / f(want) - 1) < 1e-12, (n, kmin, m, a, b, c, got, want)
     assert ffk.rule_of_thumb_calibrated(100, 10.0, 1.0, 0.0, 0.0, 1.0) == -1
     assert ffk.rule_of_thumb_calibrated(0, 10.0, 1.0, 1.0, 0.0, 1.0) == -1
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    """No fallback: without the built library every call raises."""
+    from paper_2212_12737_amd import ffk
+    monkeypatch.setattr(ffk, "_lib", None)
+    monkeypatch.setattr(ffk, "LIB_PATH", str(tmp_path / "libffkrr.so"))
+    with pytest.raises(RuntimeError, match="not built"):
+        ffk.lib()
+    with pytest.raises(RuntimeError, match="not built"):
+        ffk.rule_of_thumb(1000)
