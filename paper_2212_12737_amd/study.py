@@ -89,7 +89,8 @@ def compare(ctx, config, label_dir, steps, arms):
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         _, rep = ffk.pcg_solve(ctx, S, P, F, cfg.lam, tol=1e-6, max_iter=40000, prec=ffk.BF16X3,
-                               refresh_every=ffk.MIXED_REFRESH, escalate=True, switch_below=ffk.MIXED_SWITCH_BELOW)
+                               refresh_every=ffk.MIXED_REFRESH, escalate=True, switch_below=ffk.MIXED_SWITCH_BELOW,
+                               switch_from=ffk.MIXED_SWITCH_FROM)
         torch.cuda.synchronize()
         t3 = time.perf_counter()
         print(json.dumps({"selection": arm, "k_eff": P.k_eff, "iters": rep.iters, "status": rep.status,
@@ -112,7 +113,7 @@ def _solve_at_k(ctx, S, F, cfg, k, arm, seed):
     t2 = time.perf_counter()
     _, rep = ffk.pcg_solve(ctx, S, P, F, cfg.lam, tol=1e-6, max_iter=3 * S.n, prec=ffk.BF16X3 if mixed else ffk.FP64,
                            refresh_every=ffk.MIXED_REFRESH, escalate=True,
-                           switch_below=ffk.MIXED_SWITCH_BELOW if mixed else 0.0)
+                           switch_below=ffk.MIXED_SWITCH_BELOW if mixed else 0.0, switch_from=ffk.MIXED_SWITCH_FROM)
     torch.cuda.synchronize()
     t3 = time.perf_counter()
     rec = {"n": S.n, "k": k, "k_eff": P.k_eff, "arm": arm, "iters": rep.iters, "iters_over_n": rep.iters / S.n,

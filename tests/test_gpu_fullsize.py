@@ -59,7 +59,7 @@ def test_full_size_products_match_oracle_rows(ffk, ctx, name):
 
 def test_workload_solve_true_residual_m21_n2000(ffk, ctx):
     """The timed solve at its full size and in its launch configuration:
-    M=21, N=2000, lambda=1e-9, k=2000 columns, FP32 L, FP64 products until
+    M=21, N=2000, lambda=1e-9, k=2000 columns, FP32 L, FP32 products until
     the recursive residual falls below the switch fraction of |F|, split BF16
     after, FP64 true-residual refreshes.  Uniform selection stands in for the
     trained network (which only chooses the columns).  The oracle's own FP64
@@ -75,7 +75,7 @@ def test_workload_solve_true_residual_m21_n2000(ffk, ctx):
     P = ffk.precond_build(ctx, S, idx, cfg.lam, store=ffk.FP32)
     alpha, rep = ffk.pcg_solve(ctx, S, P, torch.as_tensor(F, device="cuda"), cfg.lam, tol=1e-6, max_iter=50000,
                                prec=ffk.BF16X3, refresh_every=ffk.MIXED_REFRESH, escalate=True,
-                               switch_below=ffk.MIXED_SWITCH_BELOW)
+                               switch_below=ffk.MIXED_SWITCH_BELOW, switch_from=ffk.MIXED_SWITCH_FROM)
     print("  iterations %d, switch %d, refreshes %d, reported residual %.3e"
           % (rep.iters, rep.switch_iter, rep.n_refresh, rep.rel_res_true), flush=True)
     assert rep.status == 0
