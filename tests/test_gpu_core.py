@@ -367,6 +367,28 @@ def test_pcg_m9_n200_mixed_precision_reaches_fp64_residual(ffk, ctx, small, prec
     assert np.linalg.norm(host(a) - ref) <= res * np.linalg.norm(F) / cfg.lam
 
 
+@pytest.mark.parametrize("prec", ["fp64", "bf16x3"])
+def test_pcg_m9_n200_alpha_within_1e6_at_tighter_tolerance(ffk, ctx, small, prec):
+    """Solved to a true residual of 1e-7, FP64 PCG and the refined split-BF16
+    path both give alpha within 1e-6 (relative) of the oracle's Cholesky
+    solution, and the fitted forces within 1e-6 too."""
+    cfg, s, S, K, idx = small
+    P = ffk.precond_build(ctx, S, idx, cfg.lam, store=ffk.FP32)
+    F = s.flat_forces()
+    mixed = prec == "bf16x3"
+    a, rep = ffk.pcg_solve(ctx, S, P, dev(F), cfg.lam, tol=1e-7, prec=ffk.PRECISIONS[prec], refresh_every=10,
+                           escalate=True, switch_below=0.7 if mixed else 0.0, switch_from=ffk.FP32 if mixed else ffk.FP64,
+                           max_iter=20000)
+    assert rep.status == 0
+    ref = osv.cholesky_solve(K, cfg.lam, F)
+    f_err = np.linalg.norm(K @ host(a) - K @ ref) / np.linalg.norm(K @ ref)
+    a_err = np.linalg.norm(host(a) - ref) / np.linalg.norm(ref)
+    print("m9_n200 tol 1e-7", prec, "iters", rep.iters, "esc", rep.n_escalations,
+          "residual %.3e forces %.3e alpha %.3e" % (oracle_relres(K, cfg.lam, host(a), F), f_err, a_err), flush=True)
+    assert oracle_relres(K, cfg.lam, host(a), F) <= 1.01e-7
+    assert f_err <= 1e-6 and a_err <= 1e-6
+
+
 @pytest.mark.parametrize("first", ["fp64", "fp32"])
 def test_pcg_m9_n200_switch_schedule(ffk, ctx, small, first):
     """First-phase products in FP64 or FP32 until the recursive residual is
