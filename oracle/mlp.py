@@ -12,7 +12,8 @@ b2 (H), w3 (H), b3 (1).
 
 Pins (tests/test_oracle_mlp.py): backward() against central finite
 differences of loss(); Adam's first step equals lr * sign(g) per coordinate;
-GELU against its series/limits.
+GELU by value, x Phi(x) at tabulated points of the normal integral and
+against an erf-free quadrature of the normal density.
 """
 from __future__ import annotations
 

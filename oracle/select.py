@@ -28,7 +28,8 @@ Readings where the paper leaves the details open:
 
 Pins (tests/test_oracle_select.py): SplitMix64 published outputs, sampler
 frequencies, Nystroem == incomplete Cholesky, monotone Schur-complement trace,
-exact leverage sum rule and the estimate's upper-bound property.
+exact leverage sum rule and the estimate's upper-bound property, per-column
+score weights on a hand-computed case.
 """
 from __future__ import annotations
 

@@ -48,6 +48,19 @@ def test_weighted_sampling_first_draw_probability():
     np.testing.assert_allclose(freq, w / w.sum(), atol=0.012)
 
 
+def test_score_weights_hand_case():
+    """N = 2 geometries of M = 3 atoms: columns 0-8 carry geometry 0's score,
+    9-17 geometry 1's; a score below the floor is raised to 1e-12."""
+    w = osel.score_weights(np.array([0.25, 3.0]), 3)
+    assert w.shape == (18,)
+    assert w[:9].tolist() == [0.25] * 9 and w[9:].tolist() == [3.0] * 9
+    w = osel.score_weights(np.array([0.0, -1.0, 5e-13, 2.0]), 3)
+    assert w[:27].tolist() == [1e-12] * 27 and w[27:].tolist() == [2.0] * 9
+    # repeated per geometry (not tiled): a tile/repeat mix-up fails here
+    w = osel.score_weights(np.array([1.0, 2.0, 3.0]), 4)
+    assert w.tolist() == [1.0] * 12 + [2.0] * 12 + [3.0] * 12
+
+
 def test_top_k_tie_break():
     keys = np.array([0.5, 0.9, 0.9, 0.1, 0.9])
     assert osel.top_k(keys, 3).tolist() == [1, 2, 4]
