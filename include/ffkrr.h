@@ -243,7 +243,11 @@ typedef struct {
   int32_t progress_every; /* > 0: print one line to stderr every so many iterations
                              (iteration, updated and true residual, precision) */
   int32_t switch_from;    /* precision of the products before the switch: FFK_FP64 (0,
-                             the default) or FFK_FP32; anything else is FFK_ERR_ARG */
+                             the default) or FFK_FP32; anything else is FFK_ERR_ARG.  An
+                             escalation before the switch ends the first phase and moves
+                             its products one rung up (FP32 -> FP64) */
+  double gap_escalate;    /* threshold of the escalation test |r_true - r| > gap_escalate
+                             |r_true| at a refresh (<= 0: 0.5) */
 } ffk_pcg_opts;
 
 typedef struct {

@@ -22,6 +22,8 @@
 // residual is large, cheap ones afterwards).
 // A breakdown (p^T q <= 0) under a reduced-precision product escalates like a
 // diverging refresh (restart from the best iterate) when `escalate` is set.
+// An escalation before the switch escalates the products of the first phase
+// (FP32 -> FP64) and ends that phase.
 #include <chrono>
 #include <cstdio>
 
@@ -33,7 +35,7 @@ enum { S_RHO0 = 0, S_RHO1 = 1, S_PAP = 2, S_RR = 3, S_ZQ = 4, S_FF = 5, S_TMP = 
 
 // Escalation tests at a refresh (reduced-precision products only).  A true
 // residual whose distance from the recursive one, |r_true - r|, exceeds
-// kGapEscalate |r_true| means the products' rounding now shows in the
+// kGapEscalate |r_true| (or the caller's threshold) means the products' rounding now shows in the
 // residual; no new best
 // true residual for kStallIterations iterations means no progress at all.  Both
 // move one rung up and keep the direction.  CG's residual norm is not
@@ -153,6 +155,7 @@ ffk_status pcg_solve(ffk_system* s, const ffk_precond* P, const double* F, doubl
   if (P) require(P->n == n, "pcg_solve: preconditioner size does not match the system");
   const int64_t max_iter = o->max_iter > 0 ? o->max_iter : n;
   const bool timing = o->timing != 0;
+  const double gap_thr = o->gap_escalate > 0.0 ? o->gap_escalate : kGapEscalate;
   double t_mvm = 0, t_prec = 0, t_vec = 0, t_ref = 0;
 
   DBuf r(n * 8), z(n * 8), p(n * 8), p2(n * 8), q(n * 8), tmp(n * 8), best(n * 8), sc(NSC * 8),
@@ -248,18 +251,28 @@ ffk_status pcg_solve(ffk_system* s, const ffk_precond* P, const double* F, doubl
   }
   int64_t hist_len = 0;
   const int refresh = o->refresh_every;
+  // Move the products one rung up from the precision now in use.  Before the
+  // switch that is `first`: the first phase ends there, one rung above it
+  // (FP32 -> FP64), whatever the reduced precision would have been.
+  auto rung_up = [&]() {
+    if (n_esc < 3) esc_iter[n_esc] = it;
+    if (hi_phase) {
+      hi_phase = false;
+      switch_iter = it;
+      prec = next_rung(first);
+    } else {
+      prec = next_rung(prec);
+    }
+    ++n_esc;
+  };
   // One rung up without a restart: the residual has just been replaced by the
   // true one, and the direction is kept (a residual replacement).
   auto step_up = [&]() {
-    if (n_esc < 3) esc_iter[n_esc] = it;
-    prec = next_rung(prec);
-    ++n_esc;
+    rung_up();
     best_it = it;
   };
   auto escalate_now = [&]() {
-    if (n_esc < 3) esc_iter[n_esc] = it;
-    prec = next_rung(prec);
-    ++n_esc;
+    rung_up();
     HIPCHK(hipMemcpyAsync(alpha, best.get(), n * 8, hipMemcpyDeviceToDevice, st));
     true_residual();
     ++n_ref;
@@ -370,7 +383,7 @@ ffk_status pcg_solve(ffk_system* s, const ffk_precond* P, const double* F, doubl
           escalate_now();
           continue;
         }
-        if (gap > kGapEscalate || it - best_it >= kStallIterations) step_up();
+        if (gap > gap_thr || it - best_it >= kStallIterations) step_up();
       }
       have_next = false;   // r was replaced: the direction must come from it
     }

@@ -35,7 +35,8 @@ class PcgOpts(ctypes.Structure):
     _fields_ = [("lam", ctypes.c_double), ("tol", ctypes.c_double), ("max_iter", ctypes.c_int64),
                 ("prec", ctypes.c_int32), ("refresh_every", ctypes.c_int32), ("escalate", ctypes.c_int32),
                 ("flexible", ctypes.c_int32), ("timing", ctypes.c_int32), ("switch_below", ctypes.c_double),
-                ("progress_every", ctypes.c_int32), ("switch_from", ctypes.c_int32)]
+                ("progress_every", ctypes.c_int32), ("switch_from", ctypes.c_int32),
+                ("gap_escalate", ctypes.c_double)]
 
 
 class PcgReport(ctypes.Structure):
@@ -351,11 +352,12 @@ MIXED_SWITCH_FROM = FP32
 def pcg_solve(ctx: Context, sys: System, P: Precond | None, F: torch.Tensor, lam: float, tol: float = 1e-6,
               max_iter: int = 0, prec: int = FP64, refresh_every: int = 10, escalate: bool = True,
               flexible: bool = False, timing: bool = False, hist_cap: int = 0, alpha: torch.Tensor | None = None,
-              switch_below: float = 0.0, progress_every: int = 0, switch_from: int = FP64, stream=None):
+              switch_below: float = 0.0, progress_every: int = 0, switch_from: int = FP64,
+              gap_escalate: float = 0.0, stream=None):
     if alpha is None:
         alpha = torch.empty(sys.n, dtype=torch.float64, device=ctx.torch_device)
     o = PcgOpts(lam, tol, max_iter, prec, refresh_every, int(escalate), int(flexible), int(timing), switch_below,
-                int(progress_every), int(switch_from))
+                int(progress_every), int(switch_from), float(gap_escalate))
     rep = PcgReport()
     hist = (ctypes.c_double * hist_cap)() if hist_cap > 0 else None
     if hist is not None:
