@@ -120,6 +120,27 @@ ffk_status ffk_system_set_symmetries(ffk_ctx* ctx, ffk_system* sys, const int32_
 ffk_status ffk_kernel_mvm(ffk_ctx* ctx, ffk_system* sys, const double* v_dev, double* y_dev,
                           double shift, ffk_precision prec, void* stream);
 
+/* ffk_kernel_mvm for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).
+ * Same arguments, result and numerics as ffk_kernel_mvm; the product's
+ * workspace (J v in the GEMM operand layouts, -W, the row-sum and split-K
+ * partials, G) lives in a fixed scratch array of 128 MiB that the library
+ * holds on every device it runs on until the process ends, and the call makes
+ * no allocation of any kind.  Conditions:
+ *  - the system's coefficients and descriptor copies for `prec` must exist:
+ *    one earlier ffk_kernel_mvm (or a solve) in that precision on `sys` builds
+ *    them; otherwise FFK_ERR_ARG;
+ *  - the workspace must fit: about N^2 (8 B FP64, 4 B FP32 and BF16 x2 arrays)
+ *    plus 3 N D doubles; N <= 3500 or so in FP64, about 5000 in split BF16 at
+ *    D = 210.  Larger systems return FFK_ERR_ARG and change nothing;
+ *  - a symmetrized system returns FFK_ERR_ARG.
+ * Every call on a GPU shares that GPU's scratch, which keeps the last call's
+ * contents (each call clears what it needs zeroed itself): two calls that
+ * overlap on one GPU (different streams or threads) race and give wrong
+ * results.  The library's kernel clocks do not time this variant. */
+ffk_status ffk_kernel_mvm_noalloc(ffk_ctx* ctx, ffk_system* sys, const double* v_dev, double* y_dev,
+                                  double shift, ffk_precision prec, void* stream);
+
 /* Profiling variant of ffk_kernel_mvm: runs the product `iters` times and
  * returns in phase_ms_host[0..4] the average milliseconds of its phases, timed
  * with HIP events on `stream`: [0] U = J v, [1] column sums of U (and the BF16

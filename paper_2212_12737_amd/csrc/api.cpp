@@ -57,6 +57,17 @@ ffk_status ffk_create(ffk_ctx** out, int device) {
   *out = nullptr;
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return FFK_ERR_ARG;
+  // the device address of the scratch array for this device, taken with the
+  // device current (the caller's current device is restored)
+  int prev = 0;
+  if (hipGetDevice(&prev) != hipSuccess) return FFK_ERR_HIP;
+  if (hipSetDevice(device) != hipSuccess) return FFK_ERR_HIP;
+  ffk_status st = guarded(nullptr, [&]() {
+    scratch_init(device);
+    return FFK_OK;
+  });
+  (void)hipSetDevice(prev);
+  if (st != FFK_OK) return st;
   ffk_ctx* c = new (std::nothrow) ffk_ctx();
   if (!c) return FFK_ERR_OOM;
   c->device = device;
@@ -126,6 +137,19 @@ ffk_status ffk_kernel_mvm(ffk_ctx* ctx, ffk_system* s, const double* v, double* 
     require(v && y && v != y, "kernel_mvm: v and y must be distinct device buffers");
     require(std::isfinite(shift), "kernel_mvm: shift must be finite");
     kernel_mvm(s, v, y, shift, (int)prec, S(stream));
+    return FFK_OK;
+  });
+}
+
+ffk_status ffk_kernel_mvm_noalloc(ffk_ctx* ctx, ffk_system* s, const double* v, double* y, double shift,
+                                  ffk_precision prec, void* stream) {
+  if (!ctx || !s) return FFK_ERR_ARG;
+  return guarded(ctx, [&]() {
+    require(v && y && v != y, "kernel_mvm_noalloc: v and y must be distinct device buffers");
+    require(std::isfinite(shift), "kernel_mvm_noalloc: shift must be finite");
+    void* base = scratch_ptr(ctx->device);
+    if (!base) fail(FFK_ERR_HIP, "kernel_mvm_noalloc: the scratch array of this device has no address");
+    kernel_mvm_scratch(s, v, y, shift, (int)prec, S(stream), base, kScratchBytes);
     return FFK_OK;
   });
 }

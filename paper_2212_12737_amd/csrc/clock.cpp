@@ -31,6 +31,7 @@ struct ClockState {
 };
 
 ClockState g_clk;
+thread_local int g_paused = 0;
 
 hipEvent_t take_event() {
   if (!g_clk.pool.empty()) {
@@ -73,8 +74,11 @@ void drain_all() {
 
 }  // namespace
 
+ClockPause::ClockPause() { ++g_paused; }
+ClockPause::~ClockPause() { --g_paused; }
+
 void clk_begin(int id, hipStream_t st) {
-  if (!g_clk.on) return;
+  if (!g_clk.on || g_paused) return;
   if (g_clk.seen[id]++ % g_clk.stride != 0) return;   // time every stride-th launch
   if (g_clk.pending.size() > 256) harvest_ready();
   hipEvent_t a = take_event();
@@ -83,7 +87,7 @@ void clk_begin(int id, hipStream_t st) {
 }
 
 void clk_end(int id, hipStream_t st) {
-  if (!g_clk.on || !g_clk.open[id]) return;
+  if (!g_clk.on || g_paused || !g_clk.open[id]) return;
   hipEvent_t b = take_event();
   HIPCHK(hipEventRecord(b, st));
   g_clk.pending.push_back(Pending{id, g_clk.open[id], b});

@@ -261,6 +261,15 @@ void kernel_mvm_phases(ffk_system* sys, const double* v, double* y, double shift
                        double* ms, hipStream_t st);
 void kernel_predict(const ffk_system* train, const ffk_system* test, const double* alpha,
                     double* F, hipStream_t st);
+// The product with its workspace carved from the device memory [base, base +
+// cap) instead of the system's own: allocates nothing.  The system's
+// coefficients and descriptor copies for prec must already exist.
+void kernel_mvm_scratch(ffk_system* sys, const double* v, double* y, double shift, int prec, hipStream_t st,
+                        void* base, size_t cap);
+// noalloc.hip -- the library's fixed scratch array on each device
+constexpr size_t kScratchBytes = (size_t)128 << 20;
+void scratch_init(int device);        // once per device, with that device current
+void* scratch_ptr(int device);        // nullptr before scratch_init
 
 // columns.hip
 // out[:, c] = K[:, cols[c]] + shift * e_{cols[c]}, column-major with leading dimension ldo.
@@ -383,6 +392,11 @@ enum ClockId {
 };
 void clk_begin(int id, hipStream_t st);
 void clk_end(int id, hipStream_t st);
+// While one exists on a thread, the clocks record nothing there.
+struct ClockPause {
+  ClockPause();
+  ~ClockPause();
+};
 void clock_enable(int stride);
 void clock_read(int id, double* total_ms, int64_t* launches);
 

@@ -664,6 +664,19 @@ static GemmOut mvm_gemms_for(const MvmArgs& a, int64_t Nr, int64_t Dk, int64_t D
 
 static size_t part_budget(int64_t N, int64_t D) { return (size_t)16 * N * D * sizeof(double); }
 
+// Device buffers of one product (all sized for the system's N and D):
+// pd (N), s (D), spart (column partials of U), G (N x D), wpart (row-sum
+// partials of W), part (split-K partials of GEMM 2, part_bytes), and the
+// product-precision operands U / UT (hi and lo for split BF16) and -W.  The
+// padding of U, UT and (FP64) -W must be zero; everything else is written
+// before it is read.
+struct MvmBufs {
+  double *pd, *s, *spart, *G, *wpart;
+  void* part;
+  size_t part_bytes;
+  void *U, *Ul, *UT, *UTl, *Wh, *Wl;
+};
+
 static void ensure_work(ffk_system* s, int prec, hipStream_t st) {
   const int64_t N = s->N, D = s->D;
   MvmWork& w = s->work;
@@ -701,6 +714,96 @@ static void ensure_work(ffk_system* s, int prec, hipStream_t st) {
   }
 }
 
+static MvmBufs handle_bufs(ffk_system* s, int prec) {
+  MvmWork& w = s->work;
+  MvmBufs b{w.pd.as<double>(), w.s.as<double>(), w.spart.as<double>(), w.G.as<double>(), w.wpart.as<double>(),
+            w.part.get(), w.part.bytes(), nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  if (prec == FFK_FP64) {
+    b.U = w.U64.get(); b.UT = w.UT64.get(); b.Wh = w.Wn64.get();
+  } else if (prec == FFK_FP32) {
+    b.U = w.U32.get(); b.UT = w.UT32.get(); b.Wh = w.Wn32.get();
+  } else {
+    b.U = w.Uh.get(); b.Ul = w.Ul.get(); b.UT = w.UTh.get(); b.UTl = w.UTl.get();
+    b.Wh = w.Wnh.get(); b.Wl = w.Wnl.get();
+  }
+  return b;
+}
+
+// The product on prepared coefficients and descriptor copies, with the
+// workspace b.  clocked: time the kernels on the library's clocks.
+static void kernel_mvm_core(ffk_system* s, const double* v, double* y, double shift, int prec, hipStream_t st,
+                            hipEvent_t* ev, double* vy_part, const MvmBufs& b) {
+  mark(ev, 0, st);
+  const int64_t N = s->N, D = s->D;
+  const int M = s->M;
+  const int64_t Nr = pad_rows(N), ldu = rup(D, 64);
+  const int nblk = cdiv(N, jv_group(N));
+  double* pd = b.pd;
+  double* cp = b.spart;
+  clk_begin(CLK_JV, st);
+  if (prec == FFK_FP64)
+    launch_jv<0>(N, M, st, s->R.as<double>(), s->pairs.as<int>(), v, s->Xc.as<double>(), N, M, D,
+                 b.U, nullptr, ldu, b.UT, nullptr, Nr, pd, cp);
+  else if (prec == FFK_FP32)
+    launch_jv<1>(N, M, st, s->R.as<double>(), s->pairs.as<int>(), v, s->Xc.as<double>(), N, M, D,
+                 b.U, nullptr, ldu, b.UT, nullptr, Nr, pd, cp);
+  else
+    launch_jv<2>(N, M, st, s->R.as<double>(), s->pairs.as<int>(), v, s->Xc.as<double>(), N, M, D,
+                 b.U, b.Ul, ldu, b.UT, b.UTl, Nr, pd, cp);
+  LAUNCHCHK();
+  clk_end(CLK_JV, st);
+  mark(ev, 1, st);
+  clk_begin(CLK_COLSUM, st);
+  k_colsum_final<<<cdiv(D, 4), 256, 0, st>>>(cp, nblk, D, b.s);
+  LAUNCHCHK();
+  clk_end(CLK_COLSUM, st);
+  mark(ev, 2, st);
+  MvmArgs a{N, N, D, s->a0, s->Xc.as<double>(), pd, b.s, b.wpart, b.G, b.part, b.part_bytes};
+  GemmOut go{1, 0};
+  CoeffSet& cs = s->coef[prec];
+  const int64_t Dk = rup(D, 64), Dr = pad_rows(D);
+  DmaOps o{};
+  o.dAh = cs.dA_hi.get();
+  o.Bc = cs.B.get();
+  o.Uh = b.U; o.UTh = b.UT; o.Wh = b.Wh;
+  if (prec == FFK_FP64) {
+    o.Xh = s->Xp64.get(); o.XTh = s->XpT64.get();
+    go = mvm_gemms_for<double, false, double>(a, Nr, Dk, Dr, o, st, ev);
+  } else if (prec == FFK_FP32) {
+    o.Xh = s->Xp32.get(); o.XTh = s->XpT32.get();
+    go = mvm_gemms_for<float, false, float>(a, Nr, Dk, Dr, o, st, ev);
+  } else {
+    const bool x3 = prec == FFK_BF16X3;
+    o.Xh = s->Xch.get(); o.XTh = s->XcTh.get();
+    if (x3) {
+      o.Xl = s->Xcl.get(); o.XTl = s->XcTl.get();
+      o.Ul = b.Ul; o.UTl = b.UTl;
+      o.dAl = cs.dA_lo.get();
+      o.Wl = b.Wl;
+      go = mvm_gemms_for<bf16_t, true, float>(a, Nr, Dk, Dr, o, st, ev);
+    } else {
+      go = mvm_gemms_for<bf16_t, false, float>(a, Nr, Dk, Dr, o, st, ev);
+    }
+  }
+  mark(ev, 4, st);
+  const int tb = M <= 64 ? 64 : 128;
+  const size_t shj = (3 * M + D) * sizeof(double);
+  clk_begin(CLK_JTG, st);
+  if (go.splits == 1)
+    k_jtg<<<N, tb, shj, st>>>(s->R.as<double>(), b.G, v, shift, M, D, y, 0, vy_part);
+  else if (prec == FFK_FP64)
+    k_jtg_reduce<double><<<N, 256, shj, st>>>(static_cast<const double*>(b.part), go.splits, N, b.s,
+                                             s->Xc.as<double>(), b.wpart, go.ntn, s->a0, s->R.as<double>(), v,
+                                             shift, M, D, y, vy_part);
+  else
+    k_jtg_reduce<float><<<N, 256, shj, st>>>(static_cast<const float*>(b.part), go.splits, N, b.s,
+                                            s->Xc.as<double>(), b.wpart, go.ntn, s->a0, s->R.as<double>(), v,
+                                            shift, M, D, y, vy_part);
+  LAUNCHCHK();
+  clk_end(CLK_JTG, st);
+  mark(ev, 5, st);
+}
+
 void kernel_mvm_ev(ffk_system* s, const double* v, double* y, double shift, int prec, hipStream_t st,
                    hipEvent_t* ev, double* vy_part = nullptr) {
   require(prec >= FFK_FP64 && prec <= FFK_BF16X3, "kernel_mvm: unknown precision");
@@ -714,82 +817,88 @@ void kernel_mvm_ev(ffk_system* s, const double* v, double* y, double shift, int 
   ensure_coeffs(s, prec, st);
   ensure_lowp_descriptor(s, prec, st);
   ensure_work(s, prec, st);
-  mark(ev, 0, st);
+  kernel_mvm_core(s, v, y, shift, prec, st, ev, vy_part, handle_bufs(s, prec));
+}
+
+// ------------------------------------------------- caller-free workspace ----
+// Zero fill of n bytes (n a multiple of 16) with 16-byte stores: a kernel
+// rather than a memset node, so that the whole product stays kernels.
+__global__ void k_zero16(uint4* __restrict__ p, int64_t n16) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = make_uint4(0u, 0u, 0u, 0u);
+}
+
+static void zero_fill(void* p, size_t bytes, hipStream_t st) {
+  const int64_t n16 = (int64_t)(bytes / 16);
+  const int blocks = (int)std::min<int64_t>(4096, std::max<int64_t>(1, (n16 + 255) / 256));
+  k_zero16<<<blocks, 256, 0, st>>>(static_cast<uint4*>(p), n16);
+  LAUNCHCHK();
+}
+
+// Carve the workspace of one product out of [base, base + cap): the fixed
+// buffers first (256-byte aligned), then the split-K partials with what is
+// left, capped at the budget the handle path uses.  Returns the bytes the
+// fixed buffers and one split need (the smallest workable cap); *b is set
+// only when that fits.
+static size_t carve_bufs(const ffk_system* s, int prec, char* base, size_t cap, MvmBufs* b) {
   const int64_t N = s->N, D = s->D;
-  const int M = s->M;
-  MvmWork& w = s->work;
-  const int64_t Nr = pad_rows(N), ldu = rup(D, 64);
-  const int nblk = cdiv(N, jv_group(N));
-  double* pd = w.pd.as<double>();
-  double* cp = w.spart.as<double>();
-  clk_begin(CLK_JV, st);
-  if (prec == FFK_FP64)
-    launch_jv<0>(N, M, st, s->R.as<double>(), s->pairs.as<int>(), v, s->Xc.as<double>(), N, M, D,
-                 w.U64.get(), nullptr, ldu, w.UT64.get(), nullptr, Nr, pd, cp);
-  else if (prec == FFK_FP32)
-    launch_jv<1>(N, M, st, s->R.as<double>(), s->pairs.as<int>(), v, s->Xc.as<double>(), N, M, D,
-                 w.U32.get(), nullptr, ldu, w.UT32.get(), nullptr, Nr, pd, cp);
-  else
-    launch_jv<2>(N, M, st, s->R.as<double>(), s->pairs.as<int>(), v, s->Xc.as<double>(), N, M, D,
-                 w.Uh.get(), w.Ul.get(), ldu, w.UTh.get(), w.UTl.get(), Nr, pd, cp);
-  LAUNCHCHK();
-  clk_end(CLK_JV, st);
-  mark(ev, 1, st);
-  clk_begin(CLK_COLSUM, st);
-  k_colsum_final<<<cdiv(D, 4), 256, 0, st>>>(cp, nblk, D, w.s.as<double>());
-  LAUNCHCHK();
-  clk_end(CLK_COLSUM, st);
-  mark(ev, 2, st);
-  MvmArgs a{N, N, D, s->a0, s->Xc.as<double>(), pd, w.s.as<double>(), w.wpart.as<double>(), w.G.as<double>(),
-            w.part.get(), w.part.bytes()};
-  GemmOut go{1, 0};
-  CoeffSet& cs = s->coef[prec];
-  const int64_t Dk = rup(D, 64), Dr = pad_rows(D);
-  DmaOps o{};
-  o.dAh = cs.dA_hi.get();
-  o.Bc = cs.B.get();
-  if (prec == FFK_FP64) {
-    o.Xh = s->Xp64.get(); o.XTh = s->XpT64.get();
-    o.Uh = w.U64.get(); o.UTh = w.UT64.get();
-    o.Wh = w.Wn64.get();
-    go = mvm_gemms_for<double, false, double>(a, Nr, Dk, Dr, o, st, ev);
-  } else if (prec == FFK_FP32) {
-    o.Xh = s->Xp32.get(); o.XTh = s->XpT32.get();
-    o.Uh = w.U32.get(); o.UTh = w.UT32.get();
-    o.Wh = w.Wn32.get();
-    go = mvm_gemms_for<float, false, float>(a, Nr, Dk, Dr, o, st, ev);
-  } else {
-    const bool x3 = prec == FFK_BF16X3;
-    o.Xh = s->Xch.get(); o.XTh = s->XcTh.get();
-    o.Uh = w.Uh.get(); o.UTh = w.UTh.get();
-    o.Wh = w.Wnh.get();
-    if (x3) {
-      o.Xl = s->Xcl.get(); o.XTl = s->XcTl.get();
-      o.Ul = w.Ul.get(); o.UTl = w.UTl.get();
-      o.dAl = cs.dA_lo.get();
-      o.Wl = w.Wnl.get();
-      go = mvm_gemms_for<bf16_t, true, float>(a, Nr, Dk, Dr, o, st, ev);
-    } else {
-      go = mvm_gemms_for<bf16_t, false, float>(a, Nr, Dk, Dr, o, st, ev);
-    }
+  const int64_t Nr = pad_rows(N), Dk = rup(D, 64), Dr = pad_rows(D);
+  const size_t es = prec == FFK_FP64 ? 8 : prec == FFK_FP32 ? 4 : 2;   // operand element size
+  const size_t ps = prec == FFK_FP64 ? 8 : 4;                            // split-K partial element size
+  const bool two = prec == FFK_BF16 || prec == FFK_BF16X3;               // hi and lo arrays
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> size_t {
+    const size_t o = off;
+    off += (bytes + 255) / 256 * 256;
+    return o;
+  };
+  const size_t o_pd = take(N * 8), o_s = take(D * 8), o_sp = take((size_t)cdiv(N, jv_group(N)) * D * 8);
+  const size_t o_G = take(N * D * 8), o_wp = take(N * (Nr / 64) * 8);
+  const size_t o_U = take(Nr * Dk * es), o_Ul = two ? take(Nr * Dk * es) : 0;
+  const size_t o_UT = take(Dr * Nr * es), o_UTl = two ? take(Dr * Nr * es) : 0;
+  const size_t o_W = take(Nr * Nr * es), o_Wl = two ? take(Nr * Nr * es) : 0;
+  const size_t o_part = off;
+  const size_t need = o_part + N * D * ps;
+  if (need > cap || !b) return need;
+  *b = MvmBufs{reinterpret_cast<double*>(base + o_pd), reinterpret_cast<double*>(base + o_s),
+               reinterpret_cast<double*>(base + o_sp), reinterpret_cast<double*>(base + o_G),
+               reinterpret_cast<double*>(base + o_wp), base + o_part,
+               std::min(cap - o_part, part_budget(N, D)),
+               base + o_U, two ? base + o_Ul : nullptr, base + o_UT, two ? base + o_UTl : nullptr,
+               base + o_W, two ? base + o_Wl : nullptr};
+  return need;
+}
+
+void kernel_mvm_scratch(ffk_system* s, const double* v, double* y, double shift, int prec, hipStream_t st,
+                        void* base, size_t cap) {
+  require(prec >= FFK_FP64 && prec <= FFK_BF16X3, "kernel_mvm_noalloc: unknown precision");
+  require(s->sym.empty(), "kernel_mvm_noalloc: a symmetrized kernel is not supported");
+  const bool prepared = s->coef[prec].ready && s->coef[FFK_FP64].ready &&
+                        (prec == FFK_FP64   ? (bool)s->Xp64
+                         : prec == FFK_FP32 ? (bool)s->Xp32
+                                            : (bool)s->Xch && (prec == FFK_BF16 || (bool)s->coef[prec].dA_lo));
+  require(prepared, "kernel_mvm_noalloc: the system's coefficients for this precision are not built yet "
+                    "(one ffk_kernel_mvm in this precision builds them)");
+  MvmBufs b{};
+  const size_t need = carve_bufs(s, prec, static_cast<char*>(base), cap, &b);
+  if (need > cap) {
+    char msg[192];
+    snprintf(msg, sizeof(msg), "kernel_mvm_noalloc: the product at N = %lld, D = %lld needs %zu bytes of scratch, "
+             "more than the %zu available", (long long)s->N, (long long)s->D, need, cap);
+    fail(FFK_ERR_ARG, msg);
   }
-  mark(ev, 4, st);
-  const int tb = M <= 64 ? 64 : 128;
-  const size_t shj = (3 * M + D) * sizeof(double);
-  clk_begin(CLK_JTG, st);
-  if (go.splits == 1)
-    k_jtg<<<N, tb, shj, st>>>(s->R.as<double>(), w.G.as<double>(), v, shift, M, D, y, 0, vy_part);
-  else if (prec == FFK_FP64)
-    k_jtg_reduce<double><<<N, 256, shj, st>>>(w.part.as<double>(), go.splits, N, w.s.as<double>(), s->Xc.as<double>(),
-                                             w.wpart.as<double>(), go.ntn, s->a0, s->R.as<double>(), v, shift, M, D, y,
-                                             vy_part);
-  else
-    k_jtg_reduce<float><<<N, 256, shj, st>>>(w.part.as<float>(), go.splits, N, w.s.as<double>(), s->Xc.as<double>(),
-                                            w.wpart.as<double>(), go.ntn, s->a0, s->R.as<double>(), v, shift, M, D, y,
-                                            vy_part);
-  LAUNCHCHK();
-  clk_end(CLK_JTG, st);
-  mark(ev, 5, st);
+  // every call shares the scratch: clear the operand padding that the
+  // GEMMs read (U and its transpose; -W in FP64, whose epilogue writes only
+  // the valid part)
+  const int64_t Nr = pad_rows(s->N), Dk = rup(s->D, 64), Dr = pad_rows(s->D);
+  const size_t es = prec == FFK_FP64 ? 8 : prec == FFK_FP32 ? 4 : 2;
+  zero_fill(b.U, Nr * Dk * es, st);
+  zero_fill(b.UT, Dr * Nr * es, st);
+  if (b.Ul) zero_fill(b.Ul, Nr * Dk * es, st);
+  if (b.UTl) zero_fill(b.UTl, Dr * Nr * es, st);
+  if (prec == FFK_FP64) zero_fill(b.Wh, Nr * Nr * es, st);
+  ClockPause pause;   // the library's clocks would create events
+  kernel_mvm_core(s, v, y, shift, prec, st, nullptr, nullptr, b);
 }
 
 void kernel_mvm(ffk_system* s, const double* v, double* y, double shift, int prec, hipStream_t st) {

@@ -64,6 +64,7 @@ _SIGS = {
     "ffk_system_info": (I32, [P, ctypes.POINTER(I64), ctypes.POINTER(I32), ctypes.POINTER(I64), ctypes.POINTER(I64)]),
     "ffk_descriptor_export": (I32, [P, P, P, P]),
     "ffk_kernel_mvm": (I32, [P, P, P, P, DBL, I32, P]),
+    "ffk_kernel_mvm_noalloc": (I32, [P, P, P, P, DBL, I32, P]),
     "ffk_kernel_mvm_phases": (I32, [P, P, P, P, DBL, I32, I32, ctypes.POINTER(DBL), P]),
     "ffk_clock_enable": (I32, [P, I32]),
     "ffk_clock_read": (I32, [P, I32, ctypes.POINTER(DBL), ctypes.POINTER(I64)]),
@@ -198,6 +199,14 @@ def kernel_mvm(ctx: Context, sys: System, v: torch.Tensor, y: torch.Tensor | Non
         y = torch.empty(sys.n, dtype=torch.float64, device=ctx.torch_device)
     ctx.check(lib().ffk_kernel_mvm(ctx.h, sys.h, _ptr(v, torch.float64), _ptr(y, torch.float64), shift, prec,
                                    _stream(stream)), "kernel_mvm")
+    return y
+
+
+def kernel_mvm_noalloc(ctx: Context, sys: System, v: torch.Tensor, y: torch.Tensor, shift: float = 0.0,
+                       prec: int = FP64, stream=None) -> torch.Tensor:
+    """ffk_kernel_mvm_noalloc: the product with the library's fixed scratch as workspace (y must be given)."""
+    ctx.check(lib().ffk_kernel_mvm_noalloc(ctx.h, sys.h, _ptr(v, torch.float64), _ptr(y, torch.float64), shift,
+                                           prec, _stream(stream)), "kernel_mvm_noalloc")
     return y
 
 
