@@ -633,16 +633,29 @@ static GemmOut mvm_gemms_dma(const MvmArgs& a, int64_t Nr, int64_t Dk, int64_t D
 
 // Tile shapes.  Small N: 64 x 64 (GEMM 1) and 128 x 128 (GEMM 2; BF16: 64 x
 // 256) by 4 waves, where the grid would otherwise leave CUs idle.  Large N:
-// the BF16 GEMMs (single and split) use 256 x 128 by 8 waves of 64 x 64 with
-// three stages; without the lo operands that is 72 KB of LDS, so two
-// workgroups share a CU and one's epilogue overlaps the other's main loop
-// (single BF16 at N = 20000: GEMM 1 2.02 -> 1.66 ms, GEMM 2 2.89 -> 2.46 ms
-// against 256 x 256 by 8 waves, which fills a CU alone).  FP32 and FP64 stay
-// at 128 x 128, which measured faster.
+// single BF16 uses 256 x 128 by 8 waves of 64 x 64 with three stages; that
+// is 72 KB of LDS, so two workgroups share a CU and one's epilogue overlaps
+// the other's main loop (at N = 20000: GEMM 1 2.02 -> 1.66 ms, GEMM 2 2.89 ->
+// 2.46 ms against 256 x 256 by 8 waves, which fills a CU alone).  Split BF16
+// (hi and lo operands) fills a CU either way and takes the larger tile
+// below.  FP32 and FP64 stay at 128 x 128, which measured faster.
 typedef DmaTile<64, 64, 2, 2, 4> TileM;        // GEMM 1 of small N: 4x more workgroups
 typedef DmaTile<128, 128, 2, 2, 4> TileS;
 typedef DmaTile<256, 128, 4, 2, 3> TileL;      // BF16 and split BF16, large N
 typedef DmaTile<64, 256, 1, 4, 3> TileW2;      // GEMM 2 of small N: one tile spans D <= 256 columns
+// Split BF16 at large N: 256 x 256 by 8 waves of 64 x 128, two stages (128
+// KB of LDS, one workgroup per CU).  Against 256 x 128 (three stages) at M =
+// 60, N = 20000: GEMM 1 4.53 -> 3.98 ms, GEMM 2 7.25 -> 6.49 ms; 5% and 4%
+// faster products at M = 42, N = 5000 and M = 21, N = 10000.  The two GEMMs'
+// tiles can be set at build time (FFK_TILE_X3_G1, FFK_TILE_X3_G2).
+#ifndef FFK_TILE_X3_G1
+#define FFK_TILE_X3_G1 DmaTile<256, 256, 4, 2, 2>
+#endif
+#ifndef FFK_TILE_X3_G2
+#define FFK_TILE_X3_G2 DmaTile<256, 256, 4, 2, 2>
+#endif
+typedef FFK_TILE_X3_G1 TileX3G1;
+typedef FFK_TILE_X3_G2 TileX3G2;
 constexpr int64_t kLargeN = 4096;
 
 template <typename T, bool X3, typename CT>
@@ -654,6 +667,8 @@ static GemmOut mvm_gemms_for(const MvmArgs& a, int64_t Nr, int64_t Dk, int64_t D
     // FP64 measured 2% slower with it
     if constexpr (sizeof(T) == 2) return mvm_gemms_dma<T, X3, CT, TileM, TileW2>(a, Nr, Dk, Dr, o, st, ev);
     return mvm_gemms_dma<T, X3, CT, TileM, TileS>(a, Nr, Dk, Dr, o, st, ev);
+  } else if constexpr (sizeof(T) == 2 && X3) {
+    return mvm_gemms_dma<T, X3, CT, TileX3G1, TileX3G2>(a, Nr, Dk, Dr, o, st, ev);
   } else if constexpr (sizeof(T) == 2) {
     return mvm_gemms_dma<T, X3, CT, TileL, TileL>(a, Nr, Dk, Dr, o, st, ev);
   } else {
