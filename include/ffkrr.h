@@ -229,7 +229,18 @@ ffk_status ffk_precond_build(ffk_ctx* ctx, ffk_system* sys, const int64_t* idx_d
  * preconditioner stays exactly SPD, its core built from the stored L).
  * ffk_precond_build picks this build by itself for FFK_FP32 storage when the
  * FP64 factor and its copy would not fit in the device's free memory. */
-enum { FFK_BUILD_LOWMEM = 1 };
+/* FFK_BUILD_MATRIX_FREE (store_L must be FFK_FP64) keeps no n x k factor: the
+ * forced-order factor interpolates K on its kept pivots S, K[:, S] = L L_SS^T
+ * with L_SS = L[S, :] lower triangular, so L = K[:, S] L_SS^-T (section 3,
+ * Eq. 5) and the apply of Eq. 4 runs as
+ *   L^T r = L_SS^-1 (K r)_S,  L t = K (L_SS^-T t scattered onto S),
+ * two FP64 kernel products on `sys` plus k x k triangular products, in place
+ * of the two passes over L.  The build still forms the FP64 factor once (to
+ * form the core lambda I + L^T L) and then frees it; the preconditioner then
+ * holds O(k^2) memory and refers to `sys`, which must stay alive and
+ * unchanged while the preconditioner is used.  ffk_precond_export forms L
+ * from the kernel's columns. */
+enum { FFK_BUILD_LOWMEM = 1, FFK_BUILD_MATRIX_FREE = 2 };
 ffk_status ffk_precond_build_ex(ffk_ctx* ctx, ffk_system* sys, const int64_t* idx_dev, int64_t k,
                                 double lambda, ffk_precision store_L, int32_t flags, ffk_precond** out,
                                 void* stream);

@@ -269,11 +269,14 @@ ffk_status ffk_precond_build_ex(ffk_ctx* ctx, ffk_system* s, const int64_t* idx,
     require(idx != nullptr, "precond_build: idx is null");
     require(k >= 1 && k <= s->n, "precond_build: need 1 <= k <= n");
     require(lambda > 0.0 && std::isfinite(lambda), "precond_build: lambda must be > 0");
-    require((flags & ~FFK_BUILD_LOWMEM) == 0, "precond_build: unknown flags");
+    require((flags & ~(FFK_BUILD_LOWMEM | FFK_BUILD_MATRIX_FREE)) == 0, "precond_build: unknown flags");
     require(!(flags & FFK_BUILD_LOWMEM) || store_L == FFK_FP32, "precond_build: the low-memory build stores FP32");
+    require(!(flags & FFK_BUILD_MATRIX_FREE) || (store_L == FFK_FP64 && !(flags & FFK_BUILD_LOWMEM)),
+            "precond_build: the matrix-free form is built from an FP64 factor (store_L = FFK_FP64, no LOWMEM)");
     check_indices(idx, k, s->n, S(stream), "precond_build");
     bool dropped = false;
-    *out = precond_build(s, idx, k, lambda, (int)store_L, (flags & FFK_BUILD_LOWMEM) != 0, &dropped, S(stream));
+    *out = precond_build(s, idx, k, lambda, (int)store_L, (flags & FFK_BUILD_LOWMEM) != 0, &dropped, S(stream),
+                         (flags & FFK_BUILD_MATRIX_FREE) != 0);
     return dropped ? FFK_WARN_RANK_DROPPED : FFK_OK;
   });
 }

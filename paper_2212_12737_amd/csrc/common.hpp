@@ -217,6 +217,14 @@ struct ffk_precond {
   ffk::DBuf y, t1, t;       // k-vectors
   ffk::DBuf work;           // partial sums of the split GEMVs
   int64_t bytes = 0;
+  // Matrix-free form (L not stored): L = K[:, S] T^T with T = L_SS^-1, the
+  // inverse of the factor's rows at the kept pivots S; the apply runs two
+  // FP64 kernel products on `sys` instead of the two passes over L.
+  bool matrix_free = false;
+  ffk_system* sys = nullptr;  // not owned; must outlive the preconditioner
+  ffk::DBuf sel;            // k_eff int64: the kept pivots, in factor order
+  ffk::DBuf Tinv, TinvT;    // T (k x k lower, column-major, ldf) and its transpose
+  ffk::DBuf q, u;           // n-vectors: K r, then the scattered T^T t and K of it
 };
 
 struct ffk_mlp {
@@ -345,7 +353,7 @@ int64_t icd_forced(ffk_system* sys, const int64_t* idx, int64_t k, double shift,
 // of an FP64 factor that is rounded afterwards; chosen automatically when the
 // FP64 factor would not fit next to its FP32 copy.
 ffk_precond* precond_build(ffk_system* sys, const int64_t* idx, int64_t k, double lambda,
-                           int store, bool lowmem, bool* dropped, hipStream_t st);
+                           int store, bool lowmem, bool* dropped, hipStream_t st, bool matrix_free = false);
 void precond_apply(const ffk_precond* P, const double* r, double* z, hipStream_t st);
 // z = M^-1 r and the block partials of r^T z in part (kRedParts doubles);
 // returns the number of partials (fixed order; sum them with sum_parts64 or

@@ -335,10 +335,25 @@ static void compact_columns(char* L, int64_t ld, int64_t esize, const std::vecto
   }
 }
 
+// Rows sel of the factor L (ld) as a k x k column-major matrix (ldf): the
+// factor's rows at its own pivots, lower triangular by construction.
+__global__ void k_rows_at(const double* __restrict__ L, int64_t ld, const int64_t* __restrict__ sel, int64_t k,
+                          int64_t ldf, double* __restrict__ out) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= k * k) return;
+  const int64_t m = e / k, j = e % k;   // column m, row j
+  out[m * ldf + j] = L[m * ld + sel[j]];
+}
+
+static void make_matrix_free(ffk_precond* P, ffk_system* s, const int64_t* idx, const std::vector<char>& kept,
+                             hipStream_t st);
+
 ffk_precond* precond_build(ffk_system* s, const int64_t* idx, int64_t k, double lambda, int store, bool lowmem,
-                           bool* dropped_any, hipStream_t st) {
+                           bool* dropped_any, hipStream_t st, bool matrix_free) {
   require(store == FFK_FP64 || store == FFK_FP32 || store == FFK_BF16,
           "precond_build: store_L must be FFK_FP64, FFK_FP32 or FFK_BF16");
+  require(!matrix_free || (store == FFK_FP64 && !lowmem),
+          "precond_build: the matrix-free form is built from an FP64 factor");
   const int64_t n = s->n;
   const int64_t ld = pad64(n);
   std::unique_ptr<ffk_precond> P(new ffk_precond());
@@ -416,10 +431,55 @@ ffk_precond* precond_build(ffk_system* s, const int64_t* idx, int64_t k, double 
   P->y.alloc(ldf * 8);
   P->t1.alloc(ldf * 8);
   P->t.alloc(ldf * 8);
-  P->work.alloc(precond_work_doubles(n, ld, ke, store) * 8);
-  P->bytes = (int64_t)(P->L.bytes() + P->Finv.bytes() + P->FinvT.bytes() + P->work.bytes() + 3 * ldf * 8);
+  if (matrix_free && keff > 0) {
+    make_matrix_free(P.get(), s, idx, kept, st);
+    P->bytes = (int64_t)(P->Finv.bytes() + P->FinvT.bytes() + P->Tinv.bytes() + P->TinvT.bytes() + P->q.bytes() +
+                         P->u.bytes() + P->sel.bytes() + 3 * ldf * 8);
+  } else {
+    P->work.alloc(precond_work_doubles(n, ld, ke, store) * 8);
+    P->bytes = (int64_t)(P->L.bytes() + P->Finv.bytes() + P->FinvT.bytes() + P->work.bytes() + 3 * ldf * 8);
+  }
   HIPCHK(hipStreamSynchronize(st));
   return P.release();
+}
+
+// The matrix-free form of a built FP64 preconditioner.  The forced-order
+// incomplete Cholesky interpolates K on its pivots: (L L^T)[:, S] = K[:, S],
+// i.e. K[:, S] = L L_SS^T with L_SS = L[S, :] lower triangular (a pivot's row
+// is zero in every later column).  Hence L = K[:, S] T^T with T = L_SS^-1,
+// and the apply needs only T, the core and two kernel products:
+//   L^T r = T (K r)_S,   L t = K (scatter_S T^T t).
+// The core lambda I + L^T L was formed from the same FP64 factor.
+static void make_matrix_free(ffk_precond* P, ffk_system* s, const int64_t* idx, const std::vector<char>& kept,
+                             hipStream_t st) {
+  const int64_t n = P->n, k = P->k_eff, ldf = P->ldf;
+  std::vector<int64_t> h_idx(kept.size()), h_sel;
+  HIPCHK(hipMemcpyAsync(h_idx.data(), idx, kept.size() * 8, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  for (size_t j = 0; j < kept.size(); ++j)
+    if (kept[j]) h_sel.push_back(h_idx[j]);
+  require((int64_t)h_sel.size() == k, "precond_build: kept pivots do not match the factor");
+  P->sel.alloc(k * 8);
+  HIPCHK(hipMemcpyAsync(P->sel.get(), h_sel.data(), k * 8, hipMemcpyHostToDevice, st));
+  P->Tinv.alloc(ldf * k * 8);
+  HIPCHK(hipMemsetAsync(P->Tinv.get(), 0, ldf * k * 8, st));
+  k_rows_at<<<cdiv(k * k, 256), 256, 0, st>>>(P->L.as<double>(), P->ld, P->sel.as<int64_t>(), k, ldf,
+                                               P->Tinv.as<double>());
+  LAUNCHCHK();
+  trtri_lower(P->Tinv.as<double>(), k, ldf, st);
+  k_zero_upper<<<cdiv(ldf * k, 256), 256, 0, st>>>(P->Tinv.as<double>(), k, ldf);
+  LAUNCHCHK();
+  P->TinvT.alloc(ldf * k * 8);
+  HIPCHK(hipMemsetAsync(P->TinvT.get(), 0, ldf * k * 8, st));
+  k_transpose_sq<<<dim3(cdiv(k, 32), cdiv(k, 32)), 256, 0, st>>>(P->Tinv.as<double>(), k, ldf,
+                                                                  P->TinvT.as<double>());
+  LAUNCHCHK();
+  HIPCHK(hipStreamSynchronize(st));
+  P->L.release();
+  P->q.alloc(n * 8);
+  P->u.alloc(n * 8);
+  P->sys = s;
+  P->matrix_free = true;
 }
 
 // ----------------------------------------------------------------- apply ----
@@ -802,6 +862,55 @@ static void apply_t(const ffk_precond* P, const double* r, double* z, hipStream_
   LAUNCHCHK();
 }
 
+__global__ void k_gather_at(const double* __restrict__ v, const int64_t* __restrict__ sel, int64_t k,
+                            double* __restrict__ out) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < k) out[j] = v[sel[j]];
+}
+__global__ void k_zero64(double* __restrict__ v, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) v[i] = 0.0;
+}
+__global__ void k_scatter_at(const double* __restrict__ w, const int64_t* __restrict__ sel, int64_t k,
+                             double* __restrict__ v) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < k) v[sel[j]] = w[j];
+}
+
+// z = lambda^-1 (r - L C^-1 L^T r) with L = K[:, S] T^T: two FP64 kernel
+// products, the two triangular products with T and the core in between
+static void apply_matrix_free(const ffk_precond* P, const double* r, double* z, hipStream_t st,
+                              double* rz_part = nullptr) {
+  const int64_t n = P->n, k = P->k_eff, ldf = P->ldf;
+  double* q = P->q.as<double>();
+  double* u = P->u.as<double>();
+  const int64_t* sel = P->sel.as<int64_t>();
+  kernel_mvm(P->sys, r, q, 0.0, FFK_FP64, st);                                   // K r
+  k_gather_at<<<cdiv(k, 256), 256, 0, st>>>(q, sel, k, P->t1.as<double>());      // (K r)_S
+  LAUNCHCHK();
+  k_tri_dots<false><<<k, 256, 0, st>>>(P->TinvT.as<double>(), ldf, k, P->t1.as<double>(), P->y.as<double>());
+  LAUNCHCHK();                                                                      // y = L^T r = T (K r)_S
+  clk_begin(CLK_CORE, st);
+  k_tri_dots<false><<<k, 256, 0, st>>>(P->FinvT.as<double>(), ldf, k, P->y.as<double>(), P->t1.as<double>());
+  LAUNCHCHK();
+  k_tri_dots<true><<<k, 256, 0, st>>>(P->Finv.as<double>(), ldf, k, P->t1.as<double>(), P->t.as<double>());
+  LAUNCHCHK();
+  clk_end(CLK_CORE, st);
+  k_tri_dots<true><<<k, 256, 0, st>>>(P->Tinv.as<double>(), ldf, k, P->t.as<double>(), P->t1.as<double>());
+  LAUNCHCHK();                                                                      // T^T t
+  k_zero64<<<cdiv(n, 256), 256, 0, st>>>(u, n);
+  LAUNCHCHK();
+  k_scatter_at<<<cdiv(k, 256), 256, 0, st>>>(P->t1.as<double>(), sel, k, u);
+  LAUNCHCHK();
+  kernel_mvm(P->sys, u, q, 0.0, FFK_FP64, st);                                   // L t = K (scatter T^T t)
+  if (!rz_part) {
+    k_finish_n<<<cdiv(n, 256), 256, 0, st>>>(q, 1, n, n, r, 1.0 / P->lambda, z);
+  } else {
+    k_finish_n_dot<<<fused_parts(n), 256, 0, st>>>(q, 1, n, n, r, 1.0 / P->lambda, z, rz_part);
+  }
+  LAUNCHCHK();
+}
+
 int64_t precond_work_doubles(int64_t n, int64_t ld, int64_t keff, int store) {
   (void)n;
   if (store == FFK_FP64) return gemv_work<double>(ld, keff);
@@ -820,7 +929,8 @@ void precond_apply(const ffk_precond* P, const double* r, double* z, hipStream_t
     LAUNCHCHK();
     return;
   }
-  if (P->store == FFK_FP64) apply_t<double>(P, r, z, st);
+  if (P->matrix_free) apply_matrix_free(P, r, z, st);
+  else if (P->store == FFK_FP64) apply_t<double>(P, r, z, st);
   else if (P->store == FFK_FP32) apply_t<float>(P, r, z, st);
   else apply_t<bf16_t>(P, r, z, st);
 }
@@ -830,6 +940,8 @@ int precond_apply_parts(const ffk_precond* P, const double* r, double* z, double
   if (P->k_eff == 0) {
     k_scale_dot<<<np, 256, 0, st>>>(r, 1.0 / P->lambda, P->n, z, part);
     LAUNCHCHK();
+  } else if (P->matrix_free) {
+    apply_matrix_free(P, r, z, st, part);
   } else if (P->store == FFK_FP64) {
     apply_t<double>(P, r, z, st, part);
   } else if (P->store == FFK_FP32) {
@@ -854,6 +966,16 @@ __global__ void k_export(const void* L, int store, int64_t n, int64_t ld, int64_
 void precond_export(const ffk_precond* P, double* L, hipStream_t st) {
   const int64_t cnt = P->n * P->k_eff;
   if (cnt == 0) return;
+  if (P->matrix_free) {
+    // L = K[:, S] T^T, formed from the kernel's columns
+    const int64_t n = P->n, k = P->k_eff;
+    DBuf C(n * k * 8);
+    kernel_columns(P->sys, P->sel.as<int64_t>(), k, C.as<double>(), n, 0.0, st);
+    gemm64((int)n, (int)k, (int)k, 1.0, View64{C.as<double>(), 1, n}, View64{P->Tinv.as<double>(), 1, P->ldf}, 0.0,
+           L, 1, n, false, st);
+    HIPCHK(hipStreamSynchronize(st));
+    return;
+  }
   k_export<<<cdiv(cnt, 256), 256, 0, st>>>(P->L.get(), P->store, P->n, P->ld, P->k_eff, L);
   LAUNCHCHK();
 }

@@ -292,6 +292,7 @@ class Precond:
         k, keff, nb = I64(), I64(), I64()
         lib().ffk_precond_info(h, ctypes.byref(k), ctypes.byref(keff), ctypes.byref(nb))
         self.k, self.k_eff, self.bytes = k.value, keff.value, nb.value
+        self.sys = None   # a matrix-free preconditioner keeps its system alive here
 
     def __del__(self):
         if getattr(self, "h", None) and _lib is not None:
@@ -299,17 +300,20 @@ class Precond:
             self.h = None
 
 
-BUILD_LOWMEM = 1
+BUILD_LOWMEM, BUILD_MATRIX_FREE = 1, 2
 
 
 def precond_build(ctx: Context, sys: System, idx: torch.Tensor, lam: float, store: int = FP64,
-                  lowmem: bool = False, stream=None) -> Precond:
+                  lowmem: bool = False, matrix_free: bool = False, stream=None) -> Precond:
     idx = idx.to(device=ctx.torch_device, dtype=torch.int64).contiguous()
     h = ctypes.c_void_p()
-    flags = BUILD_LOWMEM if lowmem else 0
+    flags = (BUILD_LOWMEM if lowmem else 0) | (BUILD_MATRIX_FREE if matrix_free else 0)
     st = ctx.check(lib().ffk_precond_build_ex(ctx.h, sys.h, _ptr(idx), idx.numel(), lam, store, flags,
                                               ctypes.byref(h), _stream(stream)), "precond_build")
-    return Precond(ctx, h, st)
+    P = Precond(ctx, h, st)
+    if matrix_free:
+        P.sys = sys
+    return P
 
 
 def precond_apply(ctx: Context, P: Precond, r: torch.Tensor, z: torch.Tensor | None = None,

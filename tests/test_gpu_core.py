@@ -267,6 +267,36 @@ def test_precond_low_memory_build(ffk, ctx, apply_case):
     assert float(r @ z) > 0
 
 
+def test_precond_matrix_free_equals_the_stored_factor(ffk, ctx, apply_case):
+    """The matrix-free form (no n x k factor kept; L = K[:, S] L_SS^-T applied
+    through two FP64 kernel products) is the same operator as the stored FP64
+    factor: the same apply, the same exported L, and a solve that meets the
+    oracle's bound."""
+    s, idx, Lo, lam, r = apply_case
+    S = ffk.descriptor_build(ctx, dev(s.R), SIGMA)
+    P = ffk.precond_build(ctx, S, dev(idx, torch.int64), lam, store=ffk.FP64)
+    Pm = ffk.precond_build(ctx, S, dev(idx, torch.int64), lam, store=ffk.FP64, matrix_free=True)
+    assert Pm.k_eff == P.k_eff == Lo.shape[1]
+    assert Pm.bytes < P.bytes
+    z = host(ffk.precond_apply(ctx, P, dev(r)))
+    zm = host(ffk.precond_apply(ctx, Pm, dev(r)))
+    print("matrix-free apply: |z_mf - z| / |z| = %.2e, %d vs %d bytes" % (relerr(zm, z), Pm.bytes, P.bytes),
+          flush=True)
+    assert relerr(zm, z) <= 1e-9
+    assert relerr(zm, osv.woodbury(Lo, lam)(r)) <= 1e-9
+    Lm = host(ffk.precond_export(ctx, Pm, S.n))
+    assert np.abs(Lm @ Lm.T - Lo @ Lo.T).max() <= 1e-10 * np.abs(Lo @ Lo.T).max()
+    K = ok.dense_kernel(s.R, SIGMA)
+    F = s.flat_forces()
+    a, rep = ffk.pcg_solve(ctx, S, Pm, dev(F), lam, tol=1e-8, prec=ffk.FP64, max_iter=5000)
+    _, rep_s = ffk.pcg_solve(ctx, S, P, dev(F), lam, tol=1e-8, prec=ffk.FP64, max_iter=5000)
+    print("  PCG to 1e-8: matrix-free %d iterations, stored %d" % (rep.iters, rep_s.iters), flush=True)
+    assert rep.status == 0 and abs(rep.iters - rep_s.iters) <= 1
+    assert oracle_relres(K, lam, host(a), F) <= 1.01e-8
+    with pytest.raises(ffk.FfkError):      # built from an FP64 factor only
+        ffk.precond_build(ctx, S, dev(idx, torch.int64), lam, store=ffk.FP32, matrix_free=True)
+
+
 def test_precond_drops_dependent_columns(ffk, ctx):
     s = system(5, 8, 305)
     S = ffk.descriptor_build(ctx, dev(s.R), SIGMA)
