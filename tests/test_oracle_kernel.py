@@ -162,3 +162,16 @@ def test_cross_mvm_uses_blocks():
         for j in range(b.N):
             ref[i * m3:(i + 1) * m3] += ok.force_kernel_block(a.R[i], b.R[j], 10.0) @ v[j * m3:(j + 1) * m3]
     np.testing.assert_allclose(y, ref, atol=1e-13 * np.abs(ref).max())
+
+
+def test_parallel_oracle_product_equals_the_serial_one():
+    """The test helper that spreads the oracle's product over processes
+    returns the oracle's own rows, in order (rectangular and square)."""
+    import oracle_parallel
+    tr = synth.make_system(6, 37, 0.05, True, 61, 62, 63)
+    te = synth.make_system(6, 11, 0.05, True, 61, 64, 63)
+    v = synth.random_vectors(tr.R.size, 5)
+    np.testing.assert_allclose(oracle_parallel.kernel_mvm(tr.R, tr.R, v, 10.0, workers=3),
+                               ok.kernel_mvm(tr.R, tr.R, v, 10.0), rtol=1e-13, atol=0)
+    np.testing.assert_allclose(oracle_parallel.kernel_mvm(te.R, tr.R, v, 10.0, workers=4),
+                               ok.kernel_mvm(te.R, tr.R, v, 10.0), rtol=1e-13, atol=0)
