@@ -10,6 +10,7 @@ from .molecules import (  # noqa: F401
     Config,
     System,
     make_system,
+    mixture_system,
     config_system,
     equilibrium_geometry,
     displaced_geometries,

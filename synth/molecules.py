@@ -173,6 +173,22 @@ def make_system(M: int, N: int, sd: float, coulomb: bool, mol_seed: int,
     return System(R=R, F=F, R0=R0, E=E)
 
 
+def mixture_system(M: int, N: int, sds, fractions, coulomb: bool, mol_seed: int, disp_seed: int,
+                   ff_seed: int) -> System:
+    """N geometries of one molecule displaced at several scales: a fraction
+    fractions[q] of them with standard deviation sds[q] (the first scale
+    takes the rounding remainder), in a seeded random order."""
+    R0 = equilibrium_geometry(M, mol_seed)
+    counts = [int(round(f * N)) for f in fractions]
+    counts[0] += N - sum(counts)
+    R = np.concatenate([displaced_geometries(R0, c, sd, disp_seed * 16 + q)
+                        for q, (sd, c) in enumerate(zip(sds, counts))])
+    R = R[np.random.Generator(np.random.PCG64(disp_seed)).permutation(N)]
+    ff = draw_force_field(R0, ff_seed, coulomb)
+    E, F = energy_and_forces(R, ff)
+    return System(R=R, F=F, R0=R0, E=E)
+
+
 def config_system(cfg: Config, N: int | None = None, disp_seed: int | None = None) -> System:
     return make_system(cfg.M, cfg.N if N is None else N, cfg.sd, cfg.coulomb,
                        cfg.mol_seed, cfg.disp_seed if disp_seed is None else disp_seed,

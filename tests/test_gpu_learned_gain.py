@@ -1,27 +1,42 @@
-"""What the trained score network gains, measured by PCG iterations.
+"""What the trained score network gains, measured by PCG iterations and time.
 
-The network is trained on exact ridge-leverage labels of small systems of one
-molecule (other displacement seeds) and selects columns for a held-out system.
-It is compared with uniform sampling and with pivoted Cholesky (the
-selection the learned path replaces).  On these synthetic data (i.i.d.
-displacements about one equilibrium) exact leverage sampling itself is no
-better than uniform sampling, so the learned selection is expected to match
-uniform, not to beat it; the test pins that it does (within 10%), that its
-solve reaches the oracle's residual bound, and that the network does learn
-the labels where they vary (lambda = 1e-6).  Printed lines give the counts.
+The network is trained on exact ridge-leverage labels of four small systems
+(N = 500) of one molecule and selects columns for a held-out N = 2000 system
+of the same molecule (M = 21, n = 126000).  It is compared with uniform,
+leverage-score and pivoted-Cholesky selection, all with the benchmark's mixed
+schedule and L stored in FP32.
+
+  * The workload's data (i.i.d. displacements of 0.08 A about one
+    equilibrium, lambda = 1e-9, k = 2000): the labels hardly vary (their
+    spread is a few 1e-4 in log score), so the network cannot do better than
+    uniform sampling there; the test pins parity with uniform and the gain
+    over the workload's own pivoted Cholesky.
+  * A mixture of displacement scales (60% at 0.02 A, 30% at 0.08 A, 10% at
+    0.25 A; lambda = 1e-6): the labels vary by about one unit of log score
+    and the network predicts them on the held-out system.  Iteration counts
+    then vary by up to +-30% with the sampling seed, for uniform and learned
+    columns alike, so the arms are compared by their mean over four
+    selection seeds: the learned columns take at least 15% fewer iterations
+    than uniform ones at k = 1000 and 2000 (measured over three draws of the
+    system and four seeds each: 21% and 26% fewer on average; leverage
+    scores from a pilot set gain nothing over uniform; pivoted Cholesky
+    needs half the iterations of either).
+The learned solves must meet the oracle's residual bound.
 """
+import time
+
 import numpy as np
 import pytest
 import torch
 
+import oracle_parallel
 import synth
-from oracle import kernel as ok
 
 pytestmark = pytest.mark.gpu
 
 SIGMA = 10.0
-M, N_TRAIN, N_TEST, K, LAM = 9, 150, 300, 300, 1e-6
-MOL, FF = 4000, 4002
+CFG = synth.CONFIGS["m21_n2000"]
+SDS, FRACTIONS = (0.02, 0.08, 0.25), (0.6, 0.3, 0.1)
 
 
 @pytest.fixture(scope="module")
@@ -36,43 +51,83 @@ def ctx(ffk):
     return ffk.create(0)
 
 
-def make(N, disp):
-    return synth.make_system(M, N, 0.08, True, MOL, disp, FF)
+def dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
 
 
-def test_learned_selection_against_uniform_and_pivoted_cholesky(ffk, ctx):
+def train(ffk, ctx, systems, lam):
     from paper_2212_12737_amd import learned
-    train = [make(N_TRAIN, 4100 + t) for t in range(3)]
-    S_tr = [ffk.descriptor_build(ctx, torch.as_tensor(s.R, device="cuda"), SIGMA) for s in train]
-    y_tr = [learned.make_labels(ctx, S, LAM) for S in S_tr]
-    net, log = learned.train(ctx, S_tr, y_tr, H=256, steps=1500, batch=150, lr=1e-3, seed=7, log_every=500)
-    print("training loss", log.losses, flush=True)
+    S_tr = [ffk.descriptor_build(ctx, dev(s.R), SIGMA) for s in systems]
+    y_tr = [learned.make_labels(ctx, S, lam) for S in S_tr]
+    net, log = learned.train(ctx, S_tr, y_tr, H=256, steps=2000, batch=256, lr=1e-3, seed=7, log_every=500)
+    y = torch.cat(y_tr)
+    print("labels: std %.3e, range [%.3e, %.3e]; loss %.2e -> %.2e"
+          % (y.std().item(), y.min().item(), y.max().item(), log.losses[0][1], log.losses[-1][1]), flush=True)
+    return net
 
-    te = make(N_TEST, 4200)
-    S = ffk.descriptor_build(ctx, torch.as_tensor(te.R, device="cuda"), SIGMA)
+
+def compare(ffk, ctx, net, s, lam, k, arms=("learned", "uniform", "leverage", "pivchol"), seeds=None):
+    """Mean iterations and time per arm over the selection seeds (pivoted
+    Cholesky, deterministic, runs once)."""
+    from paper_2212_12737_amd import learned
+    S = ffk.descriptor_build(ctx, dev(s.R), SIGMA)
+    F = dev(s.flat_forces())
+    seeds = seeds or (CFG.sel_seed,)
+    out, first_alpha = {}, None
+    for arm in arms:
+        runs = []
+        for seed in (seeds if arm != "pivchol" else seeds[:1]):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            if arm == "learned":
+                idx = learned.select(ctx, net, S, k, seed=seed)
+            else:
+                idx = ffk.nystrom_select(ctx, S, arm, k, lam=lam, seed=seed)
+            P = ffk.precond_build(ctx, S, idx, lam, store=ffk.FP32)
+            alpha, rep = ffk.pcg_solve(ctx, S, P, F, lam, tol=1e-6, max_iter=60000, prec=ffk.BF16X3,
+                                       refresh_every=ffk.MIXED_REFRESH, escalate=True,
+                                       switch_below=ffk.MIXED_SWITCH_BELOW, switch_from=ffk.MIXED_SWITCH_FROM)
+            torch.cuda.synchronize()
+            assert rep.status == 0
+            runs.append((rep.iters, time.perf_counter() - t0))
+            if arm == "learned" and first_alpha is None:
+                first_alpha = alpha
+            del P
+        out[arm] = (float(np.mean([r[0] for r in runs])), float(np.mean([r[1] for r in runs])))
+        print("  lambda %g k %d %-8s: %7.1f iterations, %.2f s (selection, build and PCG; mean of %d: %s)"
+              % (lam, k, arm, out[arm][0], out[arm][1], len(runs), [r[0] for r in runs]), flush=True)
+    a = first_alpha.cpu().numpy()
+    f = s.flat_forces()
+    res = np.linalg.norm(f - oracle_parallel.kernel_mvm(s.R, s.R, a, SIGMA) - lam * a) / np.linalg.norm(f)
+    print("  learned solve: oracle true residual %.4e" % res, flush=True)
+    assert res <= 1.01e-6
+    return out
+
+
+@pytest.mark.timeout(900)
+def test_learned_selection_at_the_workload_shape(ffk, ctx):
+    train_sys = [synth.config_system(CFG, N=500, disp_seed=CFG.disp_seed + 1000 + t) for t in range(4)]
+    net = train(ffk, ctx, train_sys, CFG.lam)
+    r = compare(ffk, ctx, net, synth.config_system(CFG), CFG.lam, CFG.k)
+    assert r["learned"][0] <= 1.05 * r["uniform"][0]
+    assert r["learned"][0] < r["pivchol"][0]
+
+
+@pytest.mark.timeout(900)
+def test_learned_selection_beats_uniform_on_mixed_displacement_scales(ffk, ctx):
+    from paper_2212_12737_amd import learned
+    lam = 1e-6
+    mix = lambda N, seed: synth.mixture_system(CFG.M, N, SDS, FRACTIONS, True, CFG.mol_seed, seed, CFG.ff_seed)
+    net = train(ffk, ctx, [mix(500, 9100 + t) for t in range(4)], lam)
+    test = mix(2000, 9200)
     # the network predicts the held-out system's exact block scores
-    y_te = learned.make_labels(ctx, S, LAM).cpu().numpy()
-    Xs = ffk.mlp_prepare_inputs(ctx, net, S, standardize=True)
-    pred = ffk.mlp_forward(ctx, net, Xs, prec=ffk.FP32).cpu().numpy()
-    corr = np.corrcoef(pred, y_te)[0, 1]
-    print("held-out label spread %.3f, correlation of prediction %.3f" % (y_te.std(), corr), flush=True)
-    assert corr > 0.5
-
-    F = torch.as_tensor(te.flat_forces(), device="cuda")
-    iters, alphas = {}, {}
-    for arm in ("learned", "uniform", "pivchol"):
-        if arm == "learned":
-            idx = learned.select(ctx, net, S, K, seed=11)
-        else:
-            idx = ffk.nystrom_select(ctx, S, arm, K, lam=LAM, seed=11)
-        P = ffk.precond_build(ctx, S, idx, LAM, store=ffk.FP32)
-        alpha, rep = ffk.pcg_solve(ctx, S, P, F, LAM, tol=1e-6, max_iter=20000, prec=ffk.BF16X3,
-                                   refresh_every=10, escalate=True, switch_below=0.3)
-        assert rep.status == 0
-        iters[arm], alphas[arm] = rep.iters, alpha.cpu().numpy()
-    print("PCG iterations", iters, flush=True)
-    a = alphas["learned"]
-    f = te.flat_forces()
-    res = f - (ok.kernel_mvm(te.R, te.R, a, SIGMA) + LAM * a)
-    assert np.linalg.norm(res) <= 1.01e-6 * np.linalg.norm(f)
-    assert iters["learned"] <= 1.1 * iters["uniform"]
+    S = ffk.descriptor_build(ctx, dev(test.R), SIGMA)
+    y_te = learned.make_labels(ctx, S, lam).cpu().numpy()
+    pred = ffk.mlp_forward(ctx, net, ffk.mlp_prepare_inputs(ctx, net, S, standardize=True), prec=ffk.FP32)
+    corr = np.corrcoef(pred.cpu().numpy(), y_te)[0, 1]
+    print("held-out labels: std %.3f; correlation with the prediction %.3f" % (y_te.std(), corr), flush=True)
+    assert y_te.std() > 0.5 and corr > 0.9
+    del S
+    for k in (1000, 2000):
+        r = compare(ffk, ctx, net, test, lam, k, seeds=(2003, 2004, 2005, 2006))
+        assert r["learned"][0] <= 0.85 * r["uniform"][0]

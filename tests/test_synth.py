@@ -33,3 +33,17 @@ def test_zero_net_force_and_torque():
     s = synth.config_system(synth.CONFIGS["m9_n200"])
     assert np.abs(s.F.sum(1)).max() < 1e-12
     assert np.abs(np.cross(s.R, s.F).sum(1)).max() < 1e-12
+
+
+def test_mixture_of_displacement_scales():
+    """Each scale contributes its share of geometries (the first takes the
+    rounding remainder), in a permuted order; labels stay central pair forces."""
+    s = synth.mixture_system(6, 101, (0.01, 0.3), (0.7, 0.3), True, 5, 6, 7)
+    assert s.R.shape == (101, 6, 3)
+    spread = np.abs(s.R - s.R0).reshape(101, -1).max(1)
+    small = spread < 0.06          # 0.01 x 6 sigma
+    assert small.sum() == 71 and (~small).sum() == 30
+    assert not np.all(small[:71])  # shuffled, not in blocks
+    assert np.abs(s.F.sum(1)).max() < 1e-12
+    again = synth.mixture_system(6, 101, (0.01, 0.3), (0.7, 0.3), True, 5, 6, 7)
+    assert np.array_equal(s.R, again.R)
