@@ -492,6 +492,47 @@ __global__ __launch_bounds__(TL::NT) void gemm_dma_kernel(DmaArgs g, Epi epi) {
     if (t + S - 1 < te) issue(t + S - 1);
     const char* st = smem + (t % S) * STAGE_BYTES;
     u4 ah[TM], bh[TN], al[X3 ? TM : 1], bl[X3 ? TN : 1];
+    if constexpr (X3 && TM * TN >= 32) {
+      // split BF16 on large wave tiles: the hi fragments, then the hi*hi
+      // products with the lo fragment reads slotted between them (two MFMAs,
+      // one LDS read), so the lo reads run while the matrix cores work.  At
+      // M = 60, N = 20000 on 256 x 256 tiles: GEMM 2 6.45 -> 6.22 ms, GEMM 1
+      // 4.01 -> 3.89 ms; issuing the lo reads right after the hi ones (one
+      // wait for all) gained nothing.
+#pragma unroll
+      for (int j = 0; j < TN; ++j)
+        bh[j] = *reinterpret_cast<const u4*>(st + NARR * A_BYTES + (wn * TN + j) * GROUP_BYTES + lane * 16);
+#pragma unroll
+      for (int i = 0; i < TM; ++i) ah[i] = *reinterpret_cast<const u4*>(st + (wm * TM + i) * GROUP_BYTES + lane * 16);
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) acc[i][j] = DmaMfma<T>::slice(ah[i], bh[j], acc[i][j], 0);
+#pragma unroll
+      for (int j = 0; j < TN; ++j)
+        bl[j] = *reinterpret_cast<const u4*>(st + NARR * A_BYTES + B_BYTES + (wn * TN + j) * GROUP_BYTES + lane * 16);
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+        al[i] = *reinterpret_cast<const u4*>(st + A_BYTES + (wm * TM + i) * GROUP_BYTES + lane * 16);
+#pragma unroll
+      for (int g = 0; g < TM + TN; ++g) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);   // two MFMAs
+        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);   // one LDS read
+      }
+      __builtin_amdgcn_sched_group_barrier(0x008, TM * TN - 2 * (TM + TN), 0);
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) acc[i][j] = DmaMfma<T>::slice(ah[i], bl[j], acc[i][j], 0);
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) acc[i][j] = DmaMfma<T>::slice(al[i], bh[j], acc[i][j], 0);
+      continue;
+    }
+
 #pragma unroll
     for (int i = 0; i < TM; ++i) {
       ah[i] = *reinterpret_cast<const u4*>(st + (wm * TM + i) * GROUP_BYTES + lane * 16);
