@@ -12,7 +12,8 @@
 // a refresh moves the product one rung up the ladder
 // BF16 -> BF16X3 -> FP32 -> FP64 when the true residual has drifted from the
 // recursive one by more than half of its norm (the products' rounding now
-// shows) or has not improved for 3000 iterations; the direction is kept.  A
+// shows; CG then restarts from the true residual, p = z) or has not improved
+// for 3000 iterations (the direction is kept).  A
 // refresh that shows divergence (10x the best true residual) also moves up a
 // rung, and restarts from the best iterate.
 // `flexible` switches beta to Polak-Ribiere, -gamma z^T q / rho.
@@ -383,7 +384,15 @@ ffk_status pcg_solve(ffk_system* s, const ffk_precond* P, const double* F, doubl
           escalate_now();
           continue;
         }
-        if (gap > gap_thr || it - best_it >= kStallIterations) step_up();
+        if (gap > gap_thr) {
+          // the recursive residual had drifted away from the true one, so
+          // the last direction was built from a wrong residual: one rung up,
+          // and CG restarts from the true residual (p = z)
+          step_up();
+          restart_direction();
+          continue;
+        }
+        if (it - best_it >= kStallIterations) step_up();
       }
       have_next = false;   // r was replaced: the direction must come from it
     }

@@ -474,6 +474,29 @@ def test_pcg_escalation_after_the_switch_climbs_the_ladder(ffk, ctx, small):
     assert oracle_relres(K, cfg.lam, host(a), F) <= 1.01e-6
 
 
+def test_pcg_restarts_after_a_gap_escalation(ffk, ctx):
+    """A nearly exact preconditioner (60 pivoted-Cholesky columns of n = 180)
+    and a tolerance below what split-BF16 products can hold: the recursive
+    residual falls to 1e-9 in a few iterations while the true one stays near
+    1e-5.  The refresh escalates and CG restarts from the true residual (p =
+    z); the solve then reaches 1e-8 within a few iterations (keeping the
+    stale direction, it stagnated for thousands)."""
+    s = synth.make_system(5, 12, 0.1, False, 31, 32, 33)
+    S = ffk.descriptor_build(ctx, dev(s.R), SIGMA)
+    K = ok.dense_kernel(s.R, SIGMA)
+    lam = 1e-4 * np.abs(K).max()
+    F = s.flat_forces()
+    idx = ffk.nystrom_select(ctx, S, "pivchol", 60)
+    P = ffk.precond_build(ctx, S, idx, lam, store=ffk.FP32)
+    a, rep = ffk.pcg_solve(ctx, S, P, dev(F), lam, tol=1e-8, max_iter=3000, prec=ffk.BF16X3, refresh_every=10,
+                           escalate=True, switch_below=0.7, switch_from=ffk.FP32)
+    res = oracle_relres(K, lam, host(a), F)
+    print("gap escalation with restart: %d iterations, %d escalations %s, oracle residual %.3e"
+          % (rep.iters, rep.n_escalations, tuple(rep.esc_iter), res), flush=True)
+    assert rep.status == 0 and res <= 1.01e-8
+    assert rep.iters <= 200 and rep.n_escalations >= 1
+
+
 def test_pcg_rejects_reduced_first_phase(ffk, ctx, small):
     cfg, s, S, K, idx = small
     P = ffk.precond_build(ctx, S, idx, cfg.lam, store=ffk.FP32)
