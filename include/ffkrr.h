@@ -103,11 +103,12 @@ ffk_status ffk_descriptor_export(ffk_ctx* ctx, const ffk_system* sys, double* X_
  * group: permutations of 0 .. M-1, no repeats, the identity included, closed
  * under composition; otherwise FFK_ERR_ARG and nothing changes.  The group of
  * the identity alone restores the plain kernel.  Afterwards every call on
- * `sys` uses K_S: ffk_kernel_mvm (FP64 only; other precisions return
- * FFK_ERR_ARG), ffk_kernel_columns, ffk_kernel_diag, selection, the
- * preconditioner, PCG, the exact leverage scores, and ffk_kernel_predict
- * with `sys` as the training system.  A product costs S rectangular FP64
- * products; the coefficients of each pair are kept between products.
+ * `sys` uses K_S: ffk_kernel_mvm (every precision), ffk_kernel_columns,
+ * ffk_kernel_diag, selection, the preconditioner, PCG, the exact leverage
+ * scores, and ffk_kernel_predict with `sys` as the training system.  The
+ * product runs as one product against the N S stacked permuted geometries
+ * (N x N S coefficient sets, built per precision on first use and kept);
+ * ffk_kernel_mvm_noalloc refuses a symmetrized system.
  * Finding the permutations (sGDML matches the molecular graph) is left to
  * the caller. */
 ffk_status ffk_system_set_symmetries(ffk_ctx* ctx, ffk_system* sys, const int32_t* perms_host, int32_t S,

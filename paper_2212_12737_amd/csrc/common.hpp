@@ -203,6 +203,14 @@ struct ffk_system {
   ffk::DBuf sym_work;
   int sym_identity = 0;     // index of the identity in the group
   ffk::RectCache rect;      // used when this system is a permuted copy
+  // The symmetrized product as one rectangular product against the stacked
+  // permuted copies: sources P_1 R, ..., P_S R (N S geometries, descriptors
+  // centred with this system's mean), N x N S coefficient sets, the
+  // product's workspace for that shape and the stacked permuted vector.
+  std::unique_ptr<ffk_system> stack;
+  ffk::CoeffSet stack_coef[4];
+  ffk::MvmWork stack_work;
+  ffk::DBuf stack_v;
 };
 
 struct ffk_precond {
@@ -246,7 +254,6 @@ namespace ffk {
 void descriptor_build(ffk_system* sys, const double* R, hipStream_t st, bool coefficients = true);
 // symmetry.hip -- the kernel symmetrized over a group of atom permutations
 void set_symmetries(ffk_system* sys, const int32_t* perms_host, int S, hipStream_t st);
-void sym_mvm(ffk_system* sys, const double* v, double* y, double shift, hipStream_t st);
 void sym_columns(const ffk_system* s, const int64_t* cols, int64_t k, double* out, int64_t ldo, double shift,
                  hipStream_t st);
 void sym_diag(const ffk_system* s, double* d, hipStream_t st);
@@ -259,7 +266,14 @@ void rect_mvm(const ffk_system* src, const ffk_system* tgt, const double* alpha,
               const double* shift_v, double shift, RectCache* cache, hipStream_t st);
 void permute_atoms(const double* a, const int32_t* p, int64_t N, int M, double* out, hipStream_t st);
 void ensure_coeffs(ffk_system* sys, int prec, hipStream_t st);
+// Coefficient sets of K(t, src) (rows t->N, columns src->N, padded); both
+// descriptors must be centred with one mean.  The pair (i, i + diag_off) is
+// at distance zero (the source is the target itself).
+void ensure_coeffs_pair(const ffk_system* t, const ffk_system* src, CoeffSet* sets, int prec, int64_t diag_off,
+                        hipStream_t st);
 void ensure_lowp_descriptor(ffk_system* sys, int prec, hipStream_t st);
+// Re-centre a system's descriptor with another mean (X_c = X - mean, |x_c|^2).
+void center_with(ffk_system* sys, const double* mean, hipStream_t st);
 
 // mvm.hip
 void kernel_mvm(ffk_system* sys, const double* v, double* y, double shift, int prec, hipStream_t st);

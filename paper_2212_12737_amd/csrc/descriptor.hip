@@ -62,35 +62,6 @@ __global__ void k_center(const double* __restrict__ X, const double* __restrict_
   if (threadIdx.x == 0) sqn[g] = red[0];
 }
 
-// Gram epilogue: Q_ij -> dA_ij, B_ij (both N x N row-major FP64).
-struct EpiCoeff {
-  const double* sqn;
-  double* dA;
-  double* B;
-  int N;
-  int64_t ld;                  // leading dimension of dA and B (padded)
-  double inv_len, a0, bcoef;   // sqrt(5)/sigma, 5/(3 sigma^2), 25/(3 sigma^4)
-  template <typename T, int TM, int TN, class Acc>
-  __device__ void run(const Acc (&acc)[TM][TN], const FragCoord& f, char*) const {
-#pragma unroll
-    for (int i = 0; i < TM; ++i)
-#pragma unroll
-      for (int j = 0; j < TN; ++j)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int r = f.row(i, v), c = f.col(j);
-          if (r < N && c < N) {
-            double r2 = sqn[r] + sqn[c] - 2.0 * (double)acc[i][j][v];
-            r2 = (r == c || r2 < 0.0) ? 0.0 : r2;
-            const double z = sqrt(r2) * inv_len;
-            const double em = expm1(-z);
-            dA[(int64_t)r * ld + c] = a0 * ((1.0 + z) * em + z);
-            B[(int64_t)r * ld + c] = -bcoef * (em + 1.0);
-          }
-        }
-  }
-};
-
 void descriptor_build(ffk_system* s, const double* R, hipStream_t st, bool coefficients) {
   const int64_t N = s->N, D = s->D;
   const int M = s->M;
@@ -254,51 +225,86 @@ void ensure_lowp_descriptor(ffk_system* s, int prec, hipStream_t st) {
   }
 }
 
-void ensure_coeffs(ffk_system* s, int prec, hipStream_t st) {
-  const int64_t N = s->N;
-  const int64_t Nr = pad_rows(N);
-  CoeffSet& c64 = s->coef[FFK_FP64];
+// Coefficients dA = a(r) - a(0), B = b(r) of the pairs (target i, source j)
+// from the Gram matrix X_t X_s^T of the centred descriptors (both centred with
+// one mean): r^2 = |x_i|^2 + |x_j|^2 - 2 x_i . x_j, set to exactly zero where
+// the source is the target itself (j = i + diag_off) or rounding makes it
+// negative.  Rows Nt, columns Ns, stored with leading dimension ld.
+struct EpiCoeffPair {
+  const double *sqr, *sqc;
+  double *dA, *B;
+  int Nt, Ns;
+  int64_t ld, diag_off;
+  double inv_len, a0, bcoef;   // sqrt(5)/sigma, 5/(3 sigma^2), 25/(3 sigma^4)
+  template <typename T, int TM, int TN, class Acc>
+  __device__ void run(const Acc (&acc)[TM][TN], const FragCoord& f, char*) const {
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int j = 0; j < TN; ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int r = f.row(i, v), c = f.col(j);
+          if (r < Nt && c < Ns) {
+            double r2 = sqr[r] + sqc[c] - 2.0 * (double)acc[i][j][v];
+            r2 = (c == r + diag_off || r2 < 0.0) ? 0.0 : r2;
+            const double z = sqrt(r2) * inv_len;
+            const double em = expm1(-z);
+            dA[(int64_t)r * ld + c] = a0 * ((1.0 + z) * em + z);
+            B[(int64_t)r * ld + c] = -bcoef * (em + 1.0);
+          }
+        }
+  }
+};
+
+void ensure_coeffs_pair(const ffk_system* t, const ffk_system* src, CoeffSet* sets, int prec, int64_t diag_off,
+                        hipStream_t st) {
+  const int64_t Nt = t->N, Ns = src->N;
+  const int64_t Ntr = pad_rows(Nt), Nsr = pad_rows(Ns);
+  CoeffSet& c64 = sets[FFK_FP64];
   if (!c64.ready) {
-    c64.dA_hi.alloc(Nr * Nr * sizeof(double));
-    c64.B.alloc(Nr * Nr * sizeof(double));
-    HIPCHK(hipMemsetAsync(c64.dA_hi.get(), 0, Nr * Nr * sizeof(double), st));
-    HIPCHK(hipMemsetAsync(c64.B.get(), 0, Nr * Nr * sizeof(double), st));
+    c64.dA_hi.alloc(Ntr * Nsr * sizeof(double));
+    c64.B.alloc(Ntr * Nsr * sizeof(double));
+    HIPCHK(hipMemsetAsync(c64.dA_hi.get(), 0, Ntr * Nsr * sizeof(double), st));
+    HIPCHK(hipMemsetAsync(c64.B.get(), 0, Ntr * Nsr * sizeof(double), st));
     ScalarArgs<double> g{};
-    g.M = (int)N;
-    g.N = (int)N;
+    g.M = (int)Nt;
+    g.N = (int)Ns;
     g.nseg = 1;
-    g.seg[0] = SegS<double>{s->Xc.as<double>(), s->D, 1, s->Xc.as<double>(), s->D, 1, (int)s->D};
-    EpiCoeff e{s->sqn.as<double>(), c64.dA_hi.as<double>(), c64.B.as<double>(), (int)N, Nr,
-               sqrt(5.0) / s->sigma, s->a0, s->bcoef};
-    dim3 grid(cdiv(N, 128), cdiv(N, 128));
-    gemm_scalar_kernel<double, 128, 128, 16, true, true, EpiCoeff><<<grid, 256, 0, st>>>(g, e);
+    g.seg[0] = SegS<double>{t->Xc.as<double>(), t->D, 1, src->Xc.as<double>(), src->D, 1, (int)t->D};
+    EpiCoeffPair e{t->sqn.as<double>(), src->sqn.as<double>(), c64.dA_hi.as<double>(), c64.B.as<double>(), (int)Nt,
+                   (int)Ns, Nsr, diag_off, sqrt(5.0) / t->sigma, t->a0, t->bcoef};
+    dim3 grid(cdiv(Ns, 128), cdiv(Nt, 128));
+    gemm_scalar_kernel<double, 128, 128, 16, true, true, EpiCoeffPair><<<grid, 256, 0, st>>>(g, e);
     LAUNCHCHK();
     c64.ready = true;
   }
   if (prec == FFK_FP64) return;
-  CoeffSet& cs = s->coef[prec];
+  CoeffSet& cs = sets[prec];
   if (cs.ready) return;
+  const int64_t cnt = Ntr * Nsr;
   if (prec == FFK_FP32) {
-    cs.dA_hi.alloc(Nr * Nr * sizeof(float));
-    cs.B.alloc(Nr * Nr * sizeof(float));
-    k_pad_copy<float><<<cdiv(Nr * Nr, 256), 256, 0, st>>>(c64.dA_hi.as<double>(), N, N, Nr, Nr, Nr,
-                                                          cs.dA_hi.as<float>());
+    cs.dA_hi.alloc(cnt * sizeof(float));
+    cs.B.alloc(cnt * sizeof(float));
+    k_pad_copy<float><<<cdiv(cnt, 256), 256, 0, st>>>(c64.dA_hi.as<double>(), Nt, Ns, Nsr, Ntr, Nsr,
+                                                      cs.dA_hi.as<float>());
     LAUNCHCHK();
-    k_pad_copy<float><<<cdiv(Nr * Nr, 256), 256, 0, st>>>(c64.B.as<double>(), N, N, Nr, Nr, Nr, cs.B.as<float>());
+    k_pad_copy<float><<<cdiv(cnt, 256), 256, 0, st>>>(c64.B.as<double>(), Nt, Ns, Nsr, Ntr, Nsr, cs.B.as<float>());
     LAUNCHCHK();
   } else {
     const bool x3 = (prec == FFK_BF16X3);
-    cs.dA_hi.alloc(Nr * Nr * 2);
-    if (x3) cs.dA_lo.alloc(Nr * Nr * 2);
-    cs.B.alloc(Nr * Nr * sizeof(float));
-    k_split_pad<<<cdiv(Nr * Nr, 256), 256, 0, st>>>(c64.dA_hi.as<double>(), N, N, Nr, Nr, Nr,
-                                                    cs.dA_hi.as<bf16_t>(),
-                                                    x3 ? cs.dA_lo.as<bf16_t>() : nullptr);
+    cs.dA_hi.alloc(cnt * 2);
+    if (x3) cs.dA_lo.alloc(cnt * 2);
+    cs.B.alloc(cnt * sizeof(float));
+    k_split_pad<<<cdiv(cnt, 256), 256, 0, st>>>(c64.dA_hi.as<double>(), Nt, Ns, Nsr, Ntr, Nsr,
+                                                cs.dA_hi.as<bf16_t>(), x3 ? cs.dA_lo.as<bf16_t>() : nullptr);
     LAUNCHCHK();
-    k_f32_pad<<<cdiv(Nr * Nr, 256), 256, 0, st>>>(c64.B.as<double>(), N, N, Nr, Nr, Nr, cs.B.as<float>());
+    k_f32_pad<<<cdiv(cnt, 256), 256, 0, st>>>(c64.B.as<double>(), Nt, Ns, Nsr, Ntr, Nsr, cs.B.as<float>());
     LAUNCHCHK();
   }
   cs.ready = true;
 }
+
+void ensure_coeffs(ffk_system* s, int prec, hipStream_t st) { ensure_coeffs_pair(s, s, s->coef, prec, 0, st); }
 
 }  // namespace ffk

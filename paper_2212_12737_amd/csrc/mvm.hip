@@ -317,7 +317,7 @@ struct EpiWT {
   const double* pd;
   CT* Wh; CT* Wl;
   double* wpart; int nparts;
-  int N;
+  int Nt, Ns;   // valid targets (rows of W) and sources (columns)
   template <typename T, int TM, int TN, class Acc>
   __device__ void run(const Acc (&acc)[TM][TN], const FragCoord& f, char* smem) const {
     static_assert(sizeof(CT) == 4 || sizeof(CT) == 2, "FP32 or BF16 storage");
@@ -333,7 +333,7 @@ struct EpiWT {
       const int c0 = f.row(i, 0);
       MT p[4];
 #pragma unroll
-      for (int v = 0; v < 4; ++v) p[v] = c0 + v < N ? (MT)pd[c0 + v] : (MT)0;
+      for (int v = 0; v < 4; ++v) p[v] = c0 + v < Ns ? (MT)pd[c0 + v] : (MT)0;
 #pragma unroll
       for (int j = 0; j < TN; ++j) {
         const int r = f.col(j);
@@ -371,7 +371,7 @@ struct EpiWT {
     const int tm = f.m0 / (16 * TM * WM);
     for (int t = threadIdx.x; t < BN; t += blockDim.x) {
       const int r = f.n0 + t;
-      if (r < N) {
+      if (r < Nt) {
         double a = 0.0;
         for (int q = 0; q < WM; ++q) a += red[q * BN + t];
         wpart[(int64_t)r * nparts + tm] = a;
@@ -581,26 +581,28 @@ struct GemmOut {
 };
 
 template <typename T, bool X3, typename CT, class TL1, class TL2>
-static GemmOut mvm_gemms_dma(const MvmArgs& a, int64_t Nr, int64_t Dk, int64_t Dr, const DmaOps& o, hipStream_t st,
-                          hipEvent_t* ev) {
-  const int64_t N = a.Nt, D = a.D;
+static GemmOut mvm_gemms_dma(const MvmArgs& a, int64_t Ntr, int64_t Nsr, int64_t Dk, int64_t Dr, const DmaOps& o,
+                             hipStream_t st, hipEvent_t* ev) {
+  const int64_t N = a.Nt, Ns = a.Ns, D = a.D;
   // FP32 and BF16: GEMM 1 computes P^T (EpiWT), so the row-sum partials of W
   // are per GEMM 1 tile row; FP64 keeps P = X_c U^T and per tile column.
   constexpr bool kTrans = sizeof(T) != 8;
-  const int ntn = (int)(Nr / (kTrans ? TL1::BM : TL1::BN));   // row-sum partials per row of W
+  const int ntn = (int)(Nsr / (kTrans ? TL1::BM : TL1::BN));   // row-sum partials per row of W (source tiles)
   {
     DmaArgs g{};
     g.nseg = 1;
     g.seg[0] = kTrans ? SegD{o.Uh, o.Ul, o.Xh, o.Xl, Dk, Dk, (int)Dk} : SegD{o.Xh, o.Xl, o.Uh, o.Ul, Dk, Dk, (int)Dk};
-    const dim3 grid((unsigned)(Nr / TL1::BN), (unsigned)(Nr / TL1::BM));
+    // FP32 / BF16: rows of the product are sources, columns targets; FP64 the reverse
+    const dim3 grid(kTrans ? (unsigned)(Ntr / TL1::BN) : (unsigned)(Nsr / TL1::BN),
+                    kTrans ? (unsigned)(Nsr / TL1::BM) : (unsigned)(Ntr / TL1::BM));
     clk_begin(CLK_GEMM1, st);
     if constexpr (kTrans) {
-      EpiWT<T, X3> e{static_cast<const float*>(o.Bc), Nr, a.pd, static_cast<T*>(o.Wh), static_cast<T*>(o.Wl),
-                     a.wpart, ntn, (int)N};
+      EpiWT<T, X3> e{static_cast<const float*>(o.Bc), Nsr, a.pd, static_cast<T*>(o.Wh), static_cast<T*>(o.Wl),
+                     a.wpart, ntn, (int)N, (int)Ns};
       gemm_dma_kernel<T, TL1, X3, decltype(e)><<<grid, TL1::NT, 0, st>>>(g, e);
     } else {
-      EpiW<T, TL1::BM> e{static_cast<const T*>(o.Bc), Nr, a.pd, static_cast<T*>(o.Wh), Nr, a.wpart, ntn, (int)N,
-                         (int)N};
+      EpiW<T, TL1::BM> e{static_cast<const T*>(o.Bc), Nsr, a.pd, static_cast<T*>(o.Wh), Nsr, a.wpart, ntn, (int)N,
+                         (int)Ns};
       gemm_dma_kernel<T, TL1, X3, decltype(e)><<<grid, TL1::NT, 0, st>>>(g, e);
     }
     LAUNCHCHK();
@@ -609,12 +611,12 @@ static GemmOut mvm_gemms_dma(const MvmArgs& a, int64_t Nr, int64_t Dk, int64_t D
   mark(ev, 3, st);
   DmaArgs g{};
   g.nseg = 2;
-  g.seg[0] = SegD{o.dAh, o.dAl, o.UTh, o.UTl, Nr, Nr, (int)Nr};
-  g.seg[1] = SegD{o.Wh, o.Wl, o.XTh, o.XTl, Nr, Nr, (int)Nr};
-  const int64_t tiles = (Dr / TL2::BN) * (Nr / TL2::BM);
-  int splits = gemm2_splits<T, X3, TL2, CT>(tiles, 2 * Nr / (64 / (int64_t)sizeof(T)), N, D);
+  g.seg[0] = SegD{o.dAh, o.dAl, o.UTh, o.UTl, Nsr, Nsr, (int)Nsr};
+  g.seg[1] = SegD{o.Wh, o.Wl, o.XTh, o.XTl, Nsr, Nsr, (int)Nsr};
+  const int64_t tiles = (Dr / TL2::BN) * (Ntr / TL2::BM);
+  int splits = gemm2_splits<T, X3, TL2, CT>(tiles, 2 * Nsr / (64 / (int64_t)sizeof(T)), N, D);
   while (splits > 1 && (size_t)splits * N * D * sizeof(CT) > a.part_bytes) splits >>= 1;
-  const dim3 grid((unsigned)(Dr / TL2::BN), (unsigned)(Nr / TL2::BM), (unsigned)splits);
+  const dim3 grid((unsigned)(Dr / TL2::BN), (unsigned)(Ntr / TL2::BM), (unsigned)splits);
   if (splits == 1) {
     EpiG<TL2::BM> e{a.s, a.Xt64, D, a.wpart, ntn, a.a0, a.G, D, (int)N, (int)D};
     clk_begin(CLK_GEMM2, st);
@@ -659,21 +661,21 @@ typedef FFK_TILE_X3_G2 TileX3G2;
 constexpr int64_t kLargeN = 4096;
 
 template <typename T, bool X3, typename CT>
-static GemmOut mvm_gemms_for(const MvmArgs& a, int64_t Nr, int64_t Dk, int64_t Dr, const DmaOps& o, hipStream_t st,
-                          hipEvent_t* ev) {
+static GemmOut mvm_gemms_for(const MvmArgs& a, int64_t Ntr, int64_t Nsr, int64_t Dk, int64_t Dr, const DmaOps& o,
+                             hipStream_t st, hipEvent_t* ev) {
   if (a.Nt < kLargeN) {
     // BF16: one 256-wide GEMM 2 tile reads [dA | -W] once instead of once per
     // 128 columns (split BF16 at N = 2000, D = 210: 30 -> 27 us); FP32 and
     // FP64 measured 2% slower with it
-    if constexpr (sizeof(T) == 2) return mvm_gemms_dma<T, X3, CT, TileM, TileW2>(a, Nr, Dk, Dr, o, st, ev);
-    return mvm_gemms_dma<T, X3, CT, TileM, TileS>(a, Nr, Dk, Dr, o, st, ev);
+    if constexpr (sizeof(T) == 2) return mvm_gemms_dma<T, X3, CT, TileM, TileW2>(a, Ntr, Nsr, Dk, Dr, o, st, ev);
+    return mvm_gemms_dma<T, X3, CT, TileM, TileS>(a, Ntr, Nsr, Dk, Dr, o, st, ev);
   } else if constexpr (sizeof(T) == 2 && X3) {
-    return mvm_gemms_dma<T, X3, CT, TileX3G1, TileX3G2>(a, Nr, Dk, Dr, o, st, ev);
+    return mvm_gemms_dma<T, X3, CT, TileX3G1, TileX3G2>(a, Ntr, Nsr, Dk, Dr, o, st, ev);
   } else if constexpr (sizeof(T) == 2) {
-    return mvm_gemms_dma<T, X3, CT, TileL, TileL>(a, Nr, Dk, Dr, o, st, ev);
+    return mvm_gemms_dma<T, X3, CT, TileL, TileL>(a, Ntr, Nsr, Dk, Dr, o, st, ev);
   } else {
     // FP32 / FP64: MFMA-bound already at 128 x 128 (measured faster than the large tiles)
-    return mvm_gemms_dma<T, X3, CT, TileS, TileS>(a, Nr, Dk, Dr, o, st, ev);
+    return mvm_gemms_dma<T, X3, CT, TileS, TileS>(a, Ntr, Nsr, Dk, Dr, o, st, ev);
   }
 }
 
@@ -692,45 +694,44 @@ struct MvmBufs {
   void *U, *Ul, *UT, *UTl, *Wh, *Wl;
 };
 
-static void ensure_work(ffk_system* s, int prec, hipStream_t st) {
-  const int64_t N = s->N, D = s->D;
-  MvmWork& w = s->work;
+// Workspace of a product with Nt targets and Ns sources (the square product:
+// Nt = Ns = N), allocated on first use and kept.
+static void ensure_work(MvmWork& w, int64_t Nt, int64_t Ns, int64_t D, int prec, hipStream_t st) {
   if (!w.pd) {
-    w.pd.alloc(N * 8);
+    w.pd.alloc(Ns * 8);
     w.s.alloc(D * 8);
-    w.spart.alloc((int64_t)cdiv(N, jv_group(N)) * D * 8);
-    w.G.alloc(N * D * 8);
-    w.wpart.alloc(N * (pad_rows(N) / 64) * 8);   // one partial per GEMM 1 tile column (tiles >= 64 wide)
-    w.part.alloc(part_budget(N, D));
+    w.spart.alloc((int64_t)cdiv(Ns, jv_group(Ns)) * D * 8);
+    w.G.alloc(Nt * D * 8);
+    w.wpart.alloc(Nt * (pad_rows(Ns) / 64) * 8);   // one partial per GEMM 1 tile of sources (tiles >= 64 wide)
+    w.part.alloc(part_budget(Nt, D));
   }
-  const int64_t Nr = pad_rows(N), Dk = rup(D, 64), Dr = pad_rows(D);
+  const int64_t Ntr = pad_rows(Nt), Nsr = pad_rows(Ns), Dk = rup(D, 64), Dr = pad_rows(D);
   // padding rows/columns stay zero: the kernels write only the valid part
   auto zeroed = [&](DBuf& b, int64_t bytes) {
     b.alloc(bytes);
     HIPCHK(hipMemsetAsync(b.get(), 0, bytes, st));
   };
   if (prec == FFK_FP64 && !w.U64) {
-    zeroed(w.U64, Nr * Dk * 8);
-    zeroed(w.UT64, Dr * Nr * 8);
-    zeroed(w.Wn64, Nr * Nr * 8);
+    zeroed(w.U64, Nsr * Dk * 8);
+    zeroed(w.UT64, Dr * Nsr * 8);
+    zeroed(w.Wn64, Ntr * Nsr * 8);
   }
   if (prec == FFK_FP32 && !w.U32) {
-    zeroed(w.U32, Nr * Dk * 4);
-    zeroed(w.UT32, Dr * Nr * 4);
-    zeroed(w.Wn32, Nr * Nr * 4);
+    zeroed(w.U32, Nsr * Dk * 4);
+    zeroed(w.UT32, Dr * Nsr * 4);
+    zeroed(w.Wn32, Ntr * Nsr * 4);
   }
   if ((prec == FFK_BF16 || prec == FFK_BF16X3) && !w.Uh) {
-    zeroed(w.Uh, Nr * Dk * 2);
-    zeroed(w.Ul, Nr * Dk * 2);
-    zeroed(w.UTh, Dr * Nr * 2);
-    zeroed(w.UTl, Dr * Nr * 2);
-    w.Wnh.alloc(Nr * Nr * 2);   // every entry is written by the GEMM 1 epilogue
-    w.Wnl.alloc(Nr * Nr * 2);
+    zeroed(w.Uh, Nsr * Dk * 2);
+    zeroed(w.Ul, Nsr * Dk * 2);
+    zeroed(w.UTh, Dr * Nsr * 2);
+    zeroed(w.UTl, Dr * Nsr * 2);
+    w.Wnh.alloc(Ntr * Nsr * 2);   // every entry is written by the GEMM 1 epilogue
+    w.Wnl.alloc(Ntr * Nsr * 2);
   }
 }
 
-static MvmBufs handle_bufs(ffk_system* s, int prec) {
-  MvmWork& w = s->work;
+static MvmBufs handle_bufs(MvmWork& w, int prec) {
   MvmBufs b{w.pd.as<double>(), w.s.as<double>(), w.spart.as<double>(), w.G.as<double>(), w.wpart.as<double>(),
             w.part.get(), w.part.bytes(), nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
   if (prec == FFK_FP64) {
@@ -744,27 +745,30 @@ static MvmBufs handle_bufs(ffk_system* s, int prec) {
   return b;
 }
 
-// The product on prepared coefficients and descriptor copies, with the
-// workspace b.  clocked: time the kernels on the library's clocks.
-static void kernel_mvm_core(ffk_system* s, const double* v, double* y, double shift, int prec, hipStream_t st,
-                            hipEvent_t* ev, double* vy_part, const MvmBufs& b) {
+// y = K(t, src) vs + shift v on prepared coefficients (coef: t->N x src->N
+// sets) and descriptor copies, with the workspace b: J v and the GEMM
+// operands over the sources, G and J^T G over the targets.  The square
+// product is t = src, vs = v.
+static void kernel_mvm_core(ffk_system* t, ffk_system* src, CoeffSet* coef, const double* vs, const double* v,
+                            double* y, double shift, int prec, hipStream_t st, hipEvent_t* ev, double* vy_part,
+                            const MvmBufs& b) {
   mark(ev, 0, st);
-  const int64_t N = s->N, D = s->D;
-  const int M = s->M;
-  const int64_t Nr = pad_rows(N), ldu = rup(D, 64);
-  const int nblk = cdiv(N, jv_group(N));
+  const int64_t N = t->N, Ns = src->N, D = t->D;
+  const int M = t->M;
+  const int64_t Ntr = pad_rows(N), Nsr = pad_rows(Ns), ldu = rup(D, 64);
+  const int nblk = cdiv(Ns, jv_group(Ns));
   double* pd = b.pd;
   double* cp = b.spart;
   clk_begin(CLK_JV, st);
   if (prec == FFK_FP64)
-    launch_jv<0>(N, M, st, s->R.as<double>(), s->pairs.as<int>(), v, s->Xc.as<double>(), N, M, D,
-                 b.U, nullptr, ldu, b.UT, nullptr, Nr, pd, cp);
+    launch_jv<0>(Ns, M, st, src->R.as<double>(), src->pairs.as<int>(), vs, src->Xc.as<double>(), Ns, M, D,
+                 b.U, nullptr, ldu, b.UT, nullptr, Nsr, pd, cp);
   else if (prec == FFK_FP32)
-    launch_jv<1>(N, M, st, s->R.as<double>(), s->pairs.as<int>(), v, s->Xc.as<double>(), N, M, D,
-                 b.U, nullptr, ldu, b.UT, nullptr, Nr, pd, cp);
+    launch_jv<1>(Ns, M, st, src->R.as<double>(), src->pairs.as<int>(), vs, src->Xc.as<double>(), Ns, M, D,
+                 b.U, nullptr, ldu, b.UT, nullptr, Nsr, pd, cp);
   else
-    launch_jv<2>(N, M, st, s->R.as<double>(), s->pairs.as<int>(), v, s->Xc.as<double>(), N, M, D,
-                 b.U, b.Ul, ldu, b.UT, b.UTl, Nr, pd, cp);
+    launch_jv<2>(Ns, M, st, src->R.as<double>(), src->pairs.as<int>(), vs, src->Xc.as<double>(), Ns, M, D,
+                 b.U, b.Ul, ldu, b.UT, b.UTl, Nsr, pd, cp);
   LAUNCHCHK();
   clk_end(CLK_JV, st);
   mark(ev, 1, st);
@@ -773,31 +777,32 @@ static void kernel_mvm_core(ffk_system* s, const double* v, double* y, double sh
   LAUNCHCHK();
   clk_end(CLK_COLSUM, st);
   mark(ev, 2, st);
-  MvmArgs a{N, N, D, s->a0, s->Xc.as<double>(), pd, b.s, b.wpart, b.G, b.part, b.part_bytes};
+  MvmArgs a{N, Ns, D, t->a0, t->Xc.as<double>(), pd, b.s, b.wpart, b.G, b.part, b.part_bytes};
   GemmOut go{1, 0};
-  CoeffSet& cs = s->coef[prec];
+  CoeffSet& cs = coef[prec];
   const int64_t Dk = rup(D, 64), Dr = pad_rows(D);
   DmaOps o{};
   o.dAh = cs.dA_hi.get();
   o.Bc = cs.B.get();
   o.Uh = b.U; o.UTh = b.UT; o.Wh = b.Wh;
+  // GEMM 1 takes the targets' descriptor, GEMM 2 the sources' (transposed)
   if (prec == FFK_FP64) {
-    o.Xh = s->Xp64.get(); o.XTh = s->XpT64.get();
-    go = mvm_gemms_for<double, false, double>(a, Nr, Dk, Dr, o, st, ev);
+    o.Xh = t->Xp64.get(); o.XTh = src->XpT64.get();
+    go = mvm_gemms_for<double, false, double>(a, Ntr, Nsr, Dk, Dr, o, st, ev);
   } else if (prec == FFK_FP32) {
-    o.Xh = s->Xp32.get(); o.XTh = s->XpT32.get();
-    go = mvm_gemms_for<float, false, float>(a, Nr, Dk, Dr, o, st, ev);
+    o.Xh = t->Xp32.get(); o.XTh = src->XpT32.get();
+    go = mvm_gemms_for<float, false, float>(a, Ntr, Nsr, Dk, Dr, o, st, ev);
   } else {
     const bool x3 = prec == FFK_BF16X3;
-    o.Xh = s->Xch.get(); o.XTh = s->XcTh.get();
+    o.Xh = t->Xch.get(); o.XTh = src->XcTh.get();
     if (x3) {
-      o.Xl = s->Xcl.get(); o.XTl = s->XcTl.get();
+      o.Xl = t->Xcl.get(); o.XTl = src->XcTl.get();
       o.Ul = b.Ul; o.UTl = b.UTl;
       o.dAl = cs.dA_lo.get();
       o.Wl = b.Wl;
-      go = mvm_gemms_for<bf16_t, true, float>(a, Nr, Dk, Dr, o, st, ev);
+      go = mvm_gemms_for<bf16_t, true, float>(a, Ntr, Nsr, Dk, Dr, o, st, ev);
     } else {
-      go = mvm_gemms_for<bf16_t, false, float>(a, Nr, Dk, Dr, o, st, ev);
+      go = mvm_gemms_for<bf16_t, false, float>(a, Ntr, Nsr, Dk, Dr, o, st, ev);
     }
   }
   mark(ev, 4, st);
@@ -805,34 +810,61 @@ static void kernel_mvm_core(ffk_system* s, const double* v, double* y, double sh
   const size_t shj = (3 * M + D) * sizeof(double);
   clk_begin(CLK_JTG, st);
   if (go.splits == 1)
-    k_jtg<<<N, tb, shj, st>>>(s->R.as<double>(), b.G, v, shift, M, D, y, 0, vy_part);
+    k_jtg<<<N, tb, shj, st>>>(t->R.as<double>(), b.G, v, shift, M, D, y, 0, vy_part);
   else if (prec == FFK_FP64)
     k_jtg_reduce<double><<<N, 256, shj, st>>>(static_cast<const double*>(b.part), go.splits, N, b.s,
-                                             s->Xc.as<double>(), b.wpart, go.ntn, s->a0, s->R.as<double>(), v,
+                                             t->Xc.as<double>(), b.wpart, go.ntn, t->a0, t->R.as<double>(), v,
                                              shift, M, D, y, vy_part);
   else
     k_jtg_reduce<float><<<N, 256, shj, st>>>(static_cast<const float*>(b.part), go.splits, N, b.s,
-                                            s->Xc.as<double>(), b.wpart, go.ntn, s->a0, s->R.as<double>(), v,
+                                            t->Xc.as<double>(), b.wpart, go.ntn, t->a0, t->R.as<double>(), v,
                                             shift, M, D, y, vy_part);
   LAUNCHCHK();
   clk_end(CLK_JTG, st);
   mark(ev, 5, st);
 }
 
+// The symmetrized product, sum_q K(R, P_q R) (Pi_q v), as one product against
+// the stacked permuted copies: v is permuted into the stacked vector, the
+// sources are the N S stacked geometries.
+__global__ void k_permute_stack(const double* __restrict__ v, const int32_t* __restrict__ perms, int S, int64_t N,
+                                int M, double* __restrict__ out) {
+  const int64_t n = N * 3 * M;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * S) return;
+  const int64_t q = e / n, r = e % n;
+  const int64_t g = r / (3 * M);
+  const int loc = (int)(r % (3 * M));
+  out[e] = v[g * 3 * M + 3 * perms[q * M + loc / 3] + loc % 3];
+}
+
+static void stack_mvm(ffk_system* s, const double* v, double* y, double shift, int prec, hipStream_t st,
+                      hipEvent_t* ev, double* vy_part) {
+  ffk_system* src = s->stack.get();
+  const int S = (int)s->sym.size();
+  ensure_coeffs_pair(s, src, s->stack_coef, prec, (int64_t)s->sym_identity * s->N, st);
+  ensure_lowp_descriptor(s, prec, st);
+  ensure_lowp_descriptor(src, prec, st);
+  ensure_work(s->stack_work, s->N, src->N, s->D, prec, st);
+  if (!s->stack_v) s->stack_v.alloc(src->n * 8);
+  k_permute_stack<<<cdiv(src->n, 256), 256, 0, st>>>(v, s->sym_perm.as<int32_t>(), S, s->N, s->M,
+                                                      s->stack_v.as<double>());
+  LAUNCHCHK();
+  kernel_mvm_core(s, src, s->stack_coef, s->stack_v.as<double>(), v, y, shift, prec, st, ev, vy_part,
+                  handle_bufs(s->stack_work, prec));
+}
+
 void kernel_mvm_ev(ffk_system* s, const double* v, double* y, double shift, int prec, hipStream_t st,
                    hipEvent_t* ev, double* vy_part = nullptr) {
   require(prec >= FFK_FP64 && prec <= FFK_BF16X3, "kernel_mvm: unknown precision");
   if (!s->sym.empty()) {
-    require(prec == FFK_FP64, "kernel_mvm: a symmetrized kernel runs its products in FP64");
-    mark(ev, 0, st);
-    sym_mvm(s, v, y, shift, st);
-    for (int i = 1; i <= 5; ++i) mark(ev, i, st);
+    stack_mvm(s, v, y, shift, prec, st, ev, vy_part);
     return;
   }
   ensure_coeffs(s, prec, st);
   ensure_lowp_descriptor(s, prec, st);
-  ensure_work(s, prec, st);
-  kernel_mvm_core(s, v, y, shift, prec, st, ev, vy_part, handle_bufs(s, prec));
+  ensure_work(s->work, s->N, s->N, s->D, prec, st);
+  kernel_mvm_core(s, s, s->coef, v, v, y, shift, prec, st, ev, vy_part, handle_bufs(s->work, prec));
 }
 
 // ------------------------------------------------- caller-free workspace ----
@@ -913,7 +945,7 @@ void kernel_mvm_scratch(ffk_system* s, const double* v, double* y, double shift,
   if (b.UTl) zero_fill(b.UTl, Dr * Nr * es, st);
   if (prec == FFK_FP64) zero_fill(b.Wh, Nr * Nr * es, st);
   ClockPause pause;   // the library's clocks would create events
-  kernel_mvm_core(s, v, y, shift, prec, st, nullptr, nullptr, b);
+  kernel_mvm_core(s, s, s->coef, v, v, y, shift, prec, st, nullptr, nullptr, b);
 }
 
 void kernel_mvm(ffk_system* s, const double* v, double* y, double shift, int prec, hipStream_t st) {
@@ -922,13 +954,9 @@ void kernel_mvm(ffk_system* s, const double* v, double* y, double shift, int pre
 
 // The product, plus the per-geometry partials of v^T y in vy_part (N doubles),
 // summed in a fixed order by the caller.  Returns the number of partials
-// written: N, or 0 for a symmetrized system (whose product does not form them).
+// written (N).
 int kernel_mvm_vy(ffk_system* s, const double* v, double* y, double shift, int prec, hipStream_t st,
                   double* vy_part) {
-  if (!s->sym.empty()) {
-    kernel_mvm_ev(s, v, y, shift, prec, st, nullptr);
-    return 0;
-  }
   kernel_mvm_ev(s, v, y, shift, prec, st, nullptr, vy_part);
   return (int)s->N;
 }
@@ -971,6 +999,12 @@ __global__ void k_center_with(const double* __restrict__ X, const double* __rest
     __syncthreads();
   }
   if (threadIdx.x == 0) sqn[g] = red[0];
+}
+
+void center_with(ffk_system* sys, const double* mean, hipStream_t st) {
+  k_center_with<<<(unsigned)sys->N, 256, 0, st>>>(sys->X.as<double>(), mean, sys->D, sys->Xc.as<double>(),
+                                                  sys->sqn.as<double>());
+  LAUNCHCHK();
 }
 
 // y (+)= K(tgt, src) alpha on the scalar FP64 engine (rectangular: targets

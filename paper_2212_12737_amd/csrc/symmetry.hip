@@ -135,6 +135,10 @@ void set_symmetries(ffk_system* s, const int32_t* perms, int S, hipStream_t st) 
   s->sym.clear();
   s->sym_perm_host.clear();
   s->max_diag = -1.0;
+  s->stack.reset();
+  for (auto& c : s->stack_coef) c = CoeffSet();
+  s->stack_work = MvmWork();
+  s->stack_v.release();
   if (S == 1) return;   // the trivial group: the plain kernel
   std::vector<int32_t> pinv((size_t)S * M);
   for (int q = 0; q < S; ++q)
@@ -161,16 +165,25 @@ void set_symmetries(ffk_system* s, const int32_t* perms, int S, hipStream_t st) 
   s->sym_perm_host.assign(perms, perms + (size_t)S * M);
   s->sym_identity = identity;
   s->sym_work.alloc(s->n * 8);
+  // the product's sources: the S permuted copies stacked, their descriptors
+  // centred with this system's mean (the kernel sees only differences)
+  std::unique_ptr<ffk_system> stk(new ffk_system());
+  stk->ctx = s->ctx;
+  stk->N = s->N * S;
+  stk->M = M;
+  stk->D = s->D;
+  stk->n = s->n * S;
+  stk->sigma = s->sigma;
+  stk->a0 = s->a0;
+  stk->bcoef = s->bcoef;
+  DBuf Rs((size_t)S * s->N * M * 3 * 8);
+  for (int q = 0; q < S; ++q)
+    HIPCHK(hipMemcpyAsync(Rs.as<double>() + (size_t)q * s->N * M * 3, s->sym[q]->R.get(), (size_t)s->N * M * 3 * 8,
+                          hipMemcpyDeviceToDevice, st));
+  descriptor_build(stk.get(), Rs.as<double>(), st, false);
+  center_with(stk.get(), s->xmean.as<double>(), st);
+  s->stack = std::move(stk);
   HIPCHK(hipStreamSynchronize(st));
-}
-
-void sym_mvm(ffk_system* s, const double* v, double* y, double shift, hipStream_t st) {
-  const int M = s->M;
-  double* vq = s->sym_work.as<double>();
-  for (size_t q = 0; q < s->sym.size(); ++q) {
-    permute_atoms(v, s->sym_perm.as<int32_t>() + q * M, s->N, M, vq, st);
-    rect_mvm(s->sym[q].get(), s, vq, y, q > 0, q == 0 ? v : nullptr, q == 0 ? shift : 0.0, &s->sym[q]->rect, st);
-  }
 }
 
 void sym_columns(const ffk_system* s, const int64_t* cols, int64_t k, double* out, int64_t ldo, double shift,
