@@ -5,9 +5,10 @@ The oracle evaluates the product one target geometry at a time
 (y_i = sum_j J_i^T H_ij J_j v_j), so a handful of rows of the
 n = 126000 to 3.6M products is cheap; the first, last and middle
 geometries and a seeded random set are compared.  Tolerances are norm-wise
-relative errors over the sampled rows: FP64 products agree to rounding, the
-FP32 and split-BF16 products (FP32 accumulation over K = 2N terms) to a few
-units of 1e-6, single BF16 to its 8-bit mantissa.
+relative errors over the sampled rows: FP64 products agree to rounding
+(1e-10), the FP32 and split-BF16 products to the 1e-6 their parity bar asks
+(measured at M = 60, N = 20000, FP32 accumulation over K = 2N = 40000 terms:
+6.9e-8 and 1.5e-7), single BF16 to its 8-bit mantissa.
 """
 import numpy as np
 import pytest
@@ -18,7 +19,7 @@ from oracle import kernel as ok
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"fp64": 1e-10, "fp32": 2e-5, "bf16x3": 2e-5, "bf16": 5e-3}
+TOL = {"fp64": 1e-10, "fp32": 1e-6, "bf16x3": 1e-6, "bf16": 5e-3}
 
 
 @pytest.fixture(scope="module")
