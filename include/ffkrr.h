@@ -131,9 +131,10 @@ ffk_status ffk_kernel_mvm(ffk_ctx* ctx, ffk_system* sys, const double* v_dev, do
  *  - the system's coefficients and descriptor copies for `prec` must exist:
  *    one earlier ffk_kernel_mvm (or a solve) in that precision on `sys` builds
  *    them; otherwise FFK_ERR_ARG;
- *  - the workspace must fit: about N^2 (8 B FP64, 4 B FP32 and BF16 x2 arrays)
- *    plus 3 N D doubles; N <= 3500 or so in FP64, about 5000 in split BF16 at
- *    D = 210.  Larger systems return FFK_ERR_ARG and change nothing;
+ *  - the workspace must fit: about N^2 (8 B FP64, 4 B FP32 and BF16 x2 arrays;
+ *    none for the BF16 products that run fused, at short D) plus 3 N D
+ *    doubles; N <= 3500 or so in FP64, about 5000 in split BF16 at D = 210.
+ *    Larger systems return FFK_ERR_ARG and change nothing;
  *  - a symmetrized system returns FFK_ERR_ARG.
  * Every call on a GPU shares that GPU's scratch, which keeps the last call's
  * contents (each call clears what it needs zeroed itself): two calls that
@@ -169,7 +170,8 @@ typedef enum {
   FFK_CLK_GEMV_T = 6,      /* preconditioner apply: L^T r partials (one pass over L) */
   FFK_CLK_GEMV_N = 7,      /* preconditioner apply: L t partials (one pass over L) */
   FFK_CLK_CORE = 8,        /* preconditioner apply: the two k x k triangular products */
-  FFK_CLK_COUNT = 9
+  FFK_CLK_FUSED = 9,       /* BF16 products at short D (<= 96; <= 128 up to N^2 = 4096^2): both GEMMs in one kernel */
+  FFK_CLK_COUNT = 10
 } ffk_clock;
 ffk_status ffk_clock_enable(ffk_ctx* ctx, int32_t stride);
 ffk_status ffk_clock_read(ffk_ctx* ctx, int32_t id, double* total_ms_host, int64_t* launches_host);

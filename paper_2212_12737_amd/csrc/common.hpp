@@ -275,6 +275,41 @@ void ensure_lowp_descriptor(ffk_system* sys, int prec, hipStream_t st);
 // Re-centre a system's descriptor with another mean (X_c = X - mean, |x_c|^2).
 void center_with(ffk_system* sys, const double* mean, hipStream_t st);
 
+// fused.hip -- the product's two dense steps in one kernel (BF16, D <= 128)
+// Operands of the fused product (layouts as in the two-GEMM form).
+struct FusedArgs {
+  const bf16_t *Uh, *Ul;     // U = J v: fragment-major, rows = sources (Nsr), K = d (KTd tiles)
+  const bf16_t *Xh, *Xl;     // X_c of the targets: fragment-major, rows = targets (Ntr), K = d
+  // [U^T | X_c^T] interleaved: fragment-major, rows = d, K = 2 Nsr (2 KTs
+  // tiles); source j at K index 8 (j / 4) + j % 4 (U) and that + 4 (X_c)
+  const bf16_t *Vh, *Vl;
+  const void* CF;            // coefficient blocks (fused_coef_build): 2 KB per 16 targets x 16 sources
+  const double* pd;          // pd_j = x_c,j . u_j, Nsr entries (zero past the sources)
+  float* part;               // splits x Nt x D partial G rows
+  double* wpart;             // Nt x splits partial row sums of W
+  int64_t KTd, KTs, Nsr;
+  int Nt, D, nchunks, splits;
+};
+constexpr int64_t kFusedMaxD = 128;
+// Where the fused form was measured faster than the two GEMMs (MI355X, split
+// BF16): D <= 96 at every size, and 96 < D <= 128 up to Nt Ns = 4096^2 (at
+// D = 120, N = 10000: 733 us fused against 676).  One rule for BF16 and split
+// BF16, which share the J v workspace and so its layout.
+inline bool use_fused(int prec, int64_t D, int64_t Nt, int64_t Ns) {
+  if (prec != FFK_BF16 && prec != FFK_BF16X3) return false;
+  return D <= 96 || (D <= kFusedMaxD && Nt * Ns <= (int64_t)4096 * 4096);
+}
+int fused_splits(int64_t Nt, int64_t Ns, int64_t D, int max_splits);
+void fused_mvm_launch(const FusedArgs& a, bool x3, hipStream_t st);
+// The X_c^T slots of the interleaved operand (split BF16) from the sources'
+// centred descriptor; zero past Ns and D.
+// The coefficient blocks of the fused product (Ntr x Nsr x 8 bytes) from the
+// FP64 dA and B (rows Nt, columns Ns, leading dimension ld).
+void fused_coef_build(const double* dA, const double* B, int64_t Nt, int64_t Ns, int64_t ld, int64_t Ntr,
+                      int64_t Nsr, void* out, hipStream_t st);
+void fused_fill_x(const double* Xc, int64_t Ns, int64_t D, int64_t Dr, int64_t Nsr, bf16_t* Vh, bf16_t* Vl,
+                  hipStream_t st);
+
 // mvm.hip
 void kernel_mvm(ffk_system* sys, const double* v, double* y, double shift, int prec, hipStream_t st);
 int kernel_mvm_vy(ffk_system* sys, const double* v, double* y, double shift, int prec, hipStream_t st,
@@ -410,7 +445,7 @@ __host__ __device__ inline int64_t frag_off(int64_t row, int64_t k, int64_t KT) 
 // clock.cpp -- per-kernel event clocks (ids match ffk_clock in ffkrr.h)
 enum ClockId {
   CLK_JV = 0, CLK_COLSUM, CLK_GEMM1, CLK_GEMM2, CLK_GEMM2_REDUCE, CLK_JTG,
-  CLK_GEMV_T, CLK_GEMV_N, CLK_CORE, CLK_COUNT
+  CLK_GEMV_T, CLK_GEMV_N, CLK_CORE, CLK_FUSED, CLK_COUNT
 };
 void clk_begin(int id, hipStream_t st);
 void clk_end(int id, hipStream_t st);

@@ -291,6 +291,10 @@ void ensure_coeffs_pair(const ffk_system* t, const ffk_system* src, CoeffSet* se
     LAUNCHCHK();
     k_pad_copy<float><<<cdiv(cnt, 256), 256, 0, st>>>(c64.B.as<double>(), Nt, Ns, Nsr, Ntr, Nsr, cs.B.as<float>());
     LAUNCHCHK();
+  } else if (use_fused(prec, t->D, Nt, Ns)) {
+    // one array in the fused product's layout: dA (hi and lo) and B
+    cs.dA_hi.alloc(cnt * 8);
+    fused_coef_build(c64.dA_hi.as<double>(), c64.B.as<double>(), Nt, Ns, Nsr, Ntr, Nsr, cs.dA_hi.get(), st);
   } else {
     const bool x3 = (prec == FFK_BF16X3);
     cs.dA_hi.alloc(cnt * 2);

@@ -26,7 +26,10 @@ static int64_t rup(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
 // GPU; large ones take 16, which keeps the column partials few.
 static int jv_group(int64_t N) { return N < 8192 ? 4 : 16; }
 
-// MODE: 0 = FP64, 1 = FP32, 2 = split BF16 (hi in U/UT, lo in Ul/UTl).
+// MODE: 0 = FP64, 1 = FP32, 2 = split BF16 (hi in U/UT, lo in Ul/UTl),
+// 3 = split BF16 with the transposed copy in the interleaved operand of the
+// fused product (geometry g at K index 8 (g / 4) + g % 4; the slots
+// 8 (g / 4) + 4 + g % 4 hold X_c^T and are not touched here).
 // U is written row-major with leading dimension ldu (BF16: fragment-major
 // with K = ldu); UT (if not null) is the transposed copy with leading
 // dimension ldut (BF16: fragment-major, K = ldut).  Padding is left untouched.
@@ -70,7 +73,7 @@ __global__ __launch_bounds__(256) void k_jv_tile(const double* __restrict__ R, c
         const int64_t o = (g0 + gl) * ldu + d;
         if (MODE == 0) static_cast<double*>(U)[o] = u;
         if (MODE == 1) static_cast<float*>(U)[o] = (float)u;
-        if (MODE == 2) {   // fragment-major, K = ldu
+        if (MODE >= 2) {   // fragment-major, K = ldu
           const float f = (float)u;
           const bf16_t h = f2bf(f);
           const int64_t of = frag_off(g0 + gl, d, ldu / 32);
@@ -89,10 +92,11 @@ __global__ __launch_bounds__(256) void k_jv_tile(const double* __restrict__ R, c
           const int64_t o = d * ldut + g0 + gl;
           if (MODE == 0) static_cast<double*>(UT)[o] = ug[gl];
           if (MODE == 1) static_cast<float*>(UT)[o] = (float)ug[gl];
-          if (MODE == 2) {   // fragment-major, K = ldut
+          if (MODE >= 2) {   // fragment-major, K = ldut
             const float f = (float)ug[gl];
             const bf16_t h = f2bf(f);
-            const int64_t of = frag_off(d, g0 + gl, ldut / 32);
+            const int64_t g = g0 + gl;
+            const int64_t of = frag_off(d, MODE == 3 ? 8 * (g >> 2) + (g & 3) : g, ldut / 32);
             static_cast<bf16_t*>(UT)[of] = h;
             static_cast<bf16_t*>(UTl)[of] = f2bf(f - bf2f(h));
           }
@@ -696,9 +700,11 @@ struct MvmBufs {
 
 // Workspace of a product with Nt targets and Ns sources (the square product:
 // Nt = Ns = N), allocated on first use and kept.
-static void ensure_work(MvmWork& w, int64_t Nt, int64_t Ns, int64_t D, int prec, hipStream_t st) {
+static void ensure_work(MvmWork& w, const ffk_system* src, int64_t Nt, int64_t D, int prec, hipStream_t st) {
+  const int64_t Ns = src->N;
   if (!w.pd) {
-    w.pd.alloc(Ns * 8);
+    w.pd.alloc(pad_rows(Ns) * 8);   // zero past the sources (the fused product reads whole chunks)
+    HIPCHK(hipMemsetAsync(w.pd.get(), 0, pad_rows(Ns) * 8, st));
     w.s.alloc(D * 8);
     w.spart.alloc((int64_t)cdiv(Ns, jv_group(Ns)) * D * 8);
     w.G.alloc(Nt * D * 8);
@@ -724,10 +730,17 @@ static void ensure_work(MvmWork& w, int64_t Nt, int64_t Ns, int64_t D, int prec,
   if ((prec == FFK_BF16 || prec == FFK_BF16X3) && !w.Uh) {
     zeroed(w.Uh, Nsr * Dk * 2);
     zeroed(w.Ul, Nsr * Dk * 2);
-    zeroed(w.UTh, Dr * Nsr * 2);
-    zeroed(w.UTl, Dr * Nsr * 2);
-    w.Wnh.alloc(Ntr * Nsr * 2);   // every entry is written by the GEMM 1 epilogue
-    w.Wnl.alloc(Ntr * Nsr * 2);
+    if (use_fused(prec, D, Nt, Ns)) {
+      // the interleaved [U^T | X_c^T] operand of the fused product
+      zeroed(w.UTh, Dr * 2 * Nsr * 2);
+      zeroed(w.UTl, Dr * 2 * Nsr * 2);
+      fused_fill_x(src->Xc.as<double>(), Ns, D, Dr, Nsr, w.UTh.as<bf16_t>(), w.UTl.as<bf16_t>(), st);
+    } else {
+      zeroed(w.UTh, Dr * Nsr * 2);
+      zeroed(w.UTl, Dr * Nsr * 2);
+      w.Wnh.alloc(Ntr * Nsr * 2);   // every entry is written by the GEMM 1 epilogue
+      w.Wnl.alloc(Ntr * Nsr * 2);
+    }
   }
 }
 
@@ -766,6 +779,9 @@ static void kernel_mvm_core(ffk_system* t, ffk_system* src, CoeffSet* coef, cons
   else if (prec == FFK_FP32)
     launch_jv<1>(Ns, M, st, src->R.as<double>(), src->pairs.as<int>(), vs, src->Xc.as<double>(), Ns, M, D,
                  b.U, nullptr, ldu, b.UT, nullptr, Nsr, pd, cp);
+  else if (use_fused(prec, D, N, Ns))
+    launch_jv<3>(Ns, M, st, src->R.as<double>(), src->pairs.as<int>(), vs, src->Xc.as<double>(), Ns, M, D,
+                 b.U, b.Ul, ldu, b.UT, b.UTl, 2 * Nsr, pd, cp);
   else
     launch_jv<2>(Ns, M, st, src->R.as<double>(), src->pairs.as<int>(), vs, src->Xc.as<double>(), Ns, M, D,
                  b.U, b.Ul, ldu, b.UT, b.UTl, Nsr, pd, cp);
@@ -792,6 +808,26 @@ static void kernel_mvm_core(ffk_system* t, ffk_system* src, CoeffSet* coef, cons
   } else if (prec == FFK_FP32) {
     o.Xh = t->Xp32.get(); o.XTh = src->XpT32.get();
     go = mvm_gemms_for<float, false, float>(a, Ntr, Nsr, Dk, Dr, o, st, ev);
+  } else if (use_fused(prec, D, N, Ns)) {
+    // both dense steps in one kernel: W stays on chip
+    const bool x3 = prec == FFK_BF16X3;
+    FusedArgs f{};
+    f.Uh = static_cast<const bf16_t*>(b.U); f.Ul = static_cast<const bf16_t*>(b.Ul);
+    f.Xh = t->Xch.as<bf16_t>(); f.Xl = t->Xcl.as<bf16_t>();
+    f.Vh = static_cast<const bf16_t*>(b.UT); f.Vl = static_cast<const bf16_t*>(b.UTl);
+    f.CF = cs.dA_hi.get();   // the fused layout of dA and B
+    f.pd = pd;
+    f.part = static_cast<float*>(b.part);
+    f.wpart = b.wpart;
+    f.KTd = Dk / 32; f.KTs = Nsr / 32; f.Nsr = Nsr;
+    f.Nt = (int)N; f.D = (int)D; f.nchunks = (int)cdiv(Ns, 16);
+    const int max_splits = (int)std::min<int64_t>({32, Nsr / 64, (int64_t)(b.part_bytes / ((size_t)N * D * 4))});
+    f.splits = fused_splits(N, Ns, D, max_splits);
+    clk_begin(CLK_FUSED, st);
+    fused_mvm_launch(f, x3, st);
+    clk_end(CLK_FUSED, st);
+    mark(ev, 3, st);
+    go = GemmOut{-f.splits, f.splits};   // negative: partials without a GEMM 2 epilogue, even for one split
   } else {
     const bool x3 = prec == FFK_BF16X3;
     o.Xh = t->Xch.get(); o.XTh = src->XcTh.get();
@@ -809,7 +845,11 @@ static void kernel_mvm_core(ffk_system* t, ffk_system* src, CoeffSet* coef, cons
   const int tb = M <= 64 ? 64 : 128;
   const size_t shj = (3 * M + D) * sizeof(double);
   clk_begin(CLK_JTG, st);
-  if (go.splits == 1)
+  if (go.splits < 0)
+    k_jtg_reduce<float><<<N, 256, shj, st>>>(static_cast<const float*>(b.part), -go.splits, N, b.s,
+                                            t->Xc.as<double>(), b.wpart, go.ntn, t->a0, t->R.as<double>(), v,
+                                            shift, M, D, y, vy_part);
+  else if (go.splits == 1)
     k_jtg<<<N, tb, shj, st>>>(t->R.as<double>(), b.G, v, shift, M, D, y, 0, vy_part);
   else if (prec == FFK_FP64)
     k_jtg_reduce<double><<<N, 256, shj, st>>>(static_cast<const double*>(b.part), go.splits, N, b.s,
@@ -845,7 +885,7 @@ static void stack_mvm(ffk_system* s, const double* v, double* y, double shift, i
   ensure_coeffs_pair(s, src, s->stack_coef, prec, (int64_t)s->sym_identity * s->N, st);
   ensure_lowp_descriptor(s, prec, st);
   ensure_lowp_descriptor(src, prec, st);
-  ensure_work(s->stack_work, s->N, src->N, s->D, prec, st);
+  ensure_work(s->stack_work, src, s->N, s->D, prec, st);
   if (!s->stack_v) s->stack_v.alloc(src->n * 8);
   k_permute_stack<<<cdiv(src->n, 256), 256, 0, st>>>(v, s->sym_perm.as<int32_t>(), S, s->N, s->M,
                                                       s->stack_v.as<double>());
@@ -863,7 +903,7 @@ void kernel_mvm_ev(ffk_system* s, const double* v, double* y, double shift, int 
   }
   ensure_coeffs(s, prec, st);
   ensure_lowp_descriptor(s, prec, st);
-  ensure_work(s->work, s->N, s->N, s->D, prec, st);
+  ensure_work(s->work, s, s->N, s->D, prec, st);
   kernel_mvm_core(s, s, s->coef, v, v, y, shift, prec, st, ev, vy_part, handle_bufs(s->work, prec));
 }
 
@@ -899,11 +939,13 @@ static size_t carve_bufs(const ffk_system* s, int prec, char* base, size_t cap, 
     off += (bytes + 255) / 256 * 256;
     return o;
   };
-  const size_t o_pd = take(N * 8), o_s = take(D * 8), o_sp = take((size_t)cdiv(N, jv_group(N)) * D * 8);
+  const bool fused = use_fused(prec, D, N, N);   // no -W buffers
+  const size_t o_pd = take(Nr * 8), o_s = take(D * 8), o_sp = take((size_t)cdiv(N, jv_group(N)) * D * 8);
   const size_t o_G = take(N * D * 8), o_wp = take(N * (Nr / 64) * 8);
   const size_t o_U = take(Nr * Dk * es), o_Ul = two ? take(Nr * Dk * es) : 0;
-  const size_t o_UT = take(Dr * Nr * es), o_UTl = two ? take(Dr * Nr * es) : 0;
-  const size_t o_W = take(Nr * Nr * es), o_Wl = two ? take(Nr * Nr * es) : 0;
+  const int64_t KV = fused ? 2 * Nr : Nr;   // K of the transposed operand (interleaved when fused)
+  const size_t o_UT = take(Dr * KV * es), o_UTl = two ? take(Dr * KV * es) : 0;
+  const size_t o_W = fused ? 0 : take(Nr * Nr * es), o_Wl = two && !fused ? take(Nr * Nr * es) : 0;
   const size_t o_part = off;
   const size_t need = o_part + N * D * ps;
   if (need > cap || !b) return need;
@@ -912,7 +954,7 @@ static size_t carve_bufs(const ffk_system* s, int prec, char* base, size_t cap, 
                reinterpret_cast<double*>(base + o_wp), base + o_part,
                std::min(cap - o_part, part_budget(N, D)),
                base + o_U, two ? base + o_Ul : nullptr, base + o_UT, two ? base + o_UTl : nullptr,
-               base + o_W, two ? base + o_Wl : nullptr};
+               fused ? nullptr : base + o_W, two && !fused ? base + o_Wl : nullptr};
   return need;
 }
 
@@ -923,7 +965,8 @@ void kernel_mvm_scratch(ffk_system* s, const double* v, double* y, double shift,
   const bool prepared = s->coef[prec].ready && s->coef[FFK_FP64].ready &&
                         (prec == FFK_FP64   ? (bool)s->Xp64
                          : prec == FFK_FP32 ? (bool)s->Xp32
-                                            : (bool)s->Xch && (prec == FFK_BF16 || (bool)s->coef[prec].dA_lo));
+                                            : (bool)s->Xch && (prec == FFK_BF16 || use_fused(prec, s->D, s->N, s->N) ||
+                                                               (bool)s->coef[prec].dA_lo));
   require(prepared, "kernel_mvm_noalloc: the system's coefficients for this precision are not built yet "
                     "(one ffk_kernel_mvm in this precision builds them)");
   MvmBufs b{};
@@ -936,13 +979,19 @@ void kernel_mvm_scratch(ffk_system* s, const double* v, double* y, double shift,
   }
   // every call shares the scratch: clear the operand padding that the
   // GEMMs read (U and its transpose; -W in FP64, whose epilogue writes only
-  // the valid part)
+  // the valid part; pd past the sources, which the fused product reads)
   const int64_t Nr = pad_rows(s->N), Dk = rup(s->D, 64), Dr = pad_rows(s->D);
   const size_t es = prec == FFK_FP64 ? 8 : prec == FFK_FP32 ? 4 : 2;
+  const bool fused = use_fused(prec, s->D, s->N, s->N);
+  const int64_t KV = fused ? 2 * Nr : Nr;
+  zero_fill(b.pd, Nr * 8, st);
   zero_fill(b.U, Nr * Dk * es, st);
-  zero_fill(b.UT, Dr * Nr * es, st);
+  zero_fill(b.UT, Dr * KV * es, st);
   if (b.Ul) zero_fill(b.Ul, Nr * Dk * es, st);
-  if (b.UTl) zero_fill(b.UTl, Dr * Nr * es, st);
+  if (b.UTl) zero_fill(b.UTl, Dr * KV * es, st);
+  if (fused)
+    fused_fill_x(s->Xc.as<double>(), s->N, s->D, Dr, Nr, static_cast<bf16_t*>(b.UT), static_cast<bf16_t*>(b.UTl),
+                 st);
   if (prec == FFK_FP64) zero_fill(b.Wh, Nr * Nr * es, st);
   ClockPause pause;   // the library's clocks would create events
   kernel_mvm_core(s, s, s->coef, v, v, y, shift, prec, st, nullptr, nullptr, b);

@@ -222,7 +222,7 @@ def kernel_mvm_phases(ctx: Context, sys: System, v: torch.Tensor, prec: int = FP
     return dict(zip(MVM_PHASES, list(ms)))
 
 
-CLOCKS = ("jv", "colsum", "gemm1", "gemm2", "gemm2_reduce", "jtg", "gemv_t", "gemv_n", "core")
+CLOCKS = ("jv", "colsum", "gemm1", "gemm2", "gemm2_reduce", "jtg", "gemv_t", "gemv_n", "core", "fused")
 
 
 def clock_enable(ctx: Context, stride: int = 1) -> None:

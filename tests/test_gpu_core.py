@@ -530,15 +530,20 @@ def test_pcg_options_flexible_timing_history_progress(ffk, ctx, small, capfd):
 
 
 def test_product_phase_clocks(ffk, ctx):
-    """kernel_mvm_phases: five positive phase times per product (J v, column
-    sums, GEMM 1 with its epilogue, GEMM 2, J^T G) in every precision."""
+    """kernel_mvm_phases: five phase times per product (J v, column sums,
+    GEMM 1 with its epilogue, GEMM 2, J^T G) in every precision.  The BF16
+    products at this width (D = 21) run both GEMMs as one fused kernel: its
+    time is the GEMM 1 phase and the GEMM 2 phase is empty."""
     s = system(7, 300, 500)
     S = ffk.descriptor_build(ctx, dev(s.R), SIGMA)
     v = dev(synth.random_vectors(S.n, 9))
     for prec in ("fp64", "fp32", "bf16x3", "bf16"):
         ph = ffk.kernel_mvm_phases(ctx, S, v, prec=ffk.PRECISIONS[prec], iters=3)
         print("phases", prec, {k: round(t, 4) for k, t in ph.items()}, flush=True)
-        assert len(ph) == 5 and all(np.isfinite(t) and t > 0.0 for t in ph.values())
+        t = list(ph.values())
+        assert len(t) == 5 and all(np.isfinite(x) and x >= 0.0 for x in t)
+        fused = prec in ("bf16x3", "bf16")
+        assert all(x > 0.0 for i, x in enumerate(t) if not (fused and i == 3))
 
 
 def test_full_rank_nystrom_preconditioner_solves_at_once(ffk, ctx):
