@@ -283,6 +283,14 @@ typedef struct {
                              its products one rung up (FP32 -> FP64) */
   double gap_escalate;    /* threshold of the escalation test |r_true - r| > gap_escalate
                              |r_true| at a refresh (<= 0: 0.5) */
+  int32_t resume;         /* 1: start from the alpha in alpha_dev (instead of alpha_0 = 0):
+                             r = F - K_lambda alpha in FP64, as at a refresh */
+  double* direction_dev;  /* optional, n float64.  With resume, on entry: the search
+                             direction to continue along (NULL: restart, p = P^-1 r).  On
+                             return (any status): the direction the next iteration would
+                             take.  Saving alpha and this direction lets a solve stop and
+                             continue later (another process, another device) the way the
+                             periodic refresh continues: true residual, direction kept */
 } ffk_pcg_opts;
 
 typedef struct {
@@ -302,8 +310,9 @@ typedef struct {
 } ffk_pcg_report;
 
 /* Solve (K + lambda I) alpha = F by preconditioned CG with P (NULL = plain CG),
- * alpha_0 = 0.  CG scalars and dot products are FP64 on the device
- * (deterministic two-stage reductions).  F, alpha: n float64. */
+ * alpha_0 = 0 (or alpha_dev's content with opts->resume).  CG scalars and dot
+ * products are FP64 on the device (deterministic two-stage reductions).
+ * F, alpha: n float64; direction_dev may not alias either. */
 ffk_status ffk_pcg_solve(ffk_ctx* ctx, ffk_system* sys, const ffk_precond* P,
                          const double* F_dev, double* alpha_dev, const ffk_pcg_opts* opts,
                          ffk_pcg_report* report, void* stream);

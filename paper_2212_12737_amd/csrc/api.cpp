@@ -318,6 +318,9 @@ ffk_status ffk_pcg_solve(ffk_ctx* ctx, ffk_system* s, const ffk_precond* P, cons
   if (!ctx || !s || !opts) return FFK_ERR_ARG;
   return guarded(ctx, [&]() {
     require(F && alpha && F != alpha, "pcg_solve: F and alpha must be distinct device buffers");
+    require(opts->resume == 0 || opts->resume == 1, "pcg_solve: resume must be 0 or 1");
+    require(!opts->direction_dev || (opts->direction_dev != F && opts->direction_dev != alpha),
+            "pcg_solve: the direction buffer may not alias F or alpha");
     return pcg_solve(s, P, F, alpha, opts, rep, S(stream));
   });
 }

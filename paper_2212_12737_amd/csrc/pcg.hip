@@ -225,8 +225,17 @@ ffk_status pcg_solve(ffk_system* s, const ffk_precond* P, const double* F, doubl
   const double fnorm = sqrt(hs[0]);
   if (!std::isfinite(fnorm)) fail(FFK_ERR_NONFINITE, "pcg_solve: F contains NaN or Inf");
 
-  HIPCHK(hipMemsetAsync(alpha, 0, n * 8, st));
-  HIPCHK(hipMemcpyAsync(R, F, n * 8, hipMemcpyDeviceToDevice, st));
+  double best_true = fnorm * fnorm;   // alpha = 0
+  double rel_upd = 1.0, rel_true = 1.0;
+  int64_t n_ref = 0;
+  if (o->resume) {
+    // continue from the caller's alpha: the true residual replaces r, as at a refresh
+    rel_true = rel_upd = fnorm > 0.0 ? sqrt(best_true = true_residual()) / fnorm : 0.0;
+    ++n_ref;
+  } else {
+    HIPCHK(hipMemsetAsync(alpha, 0, n * 8, st));
+    HIPCHK(hipMemcpyAsync(R, F, n * 8, hipMemcpyDeviceToDevice, st));
+  }
   HIPCHK(hipMemcpyAsync(best.get(), alpha, n * 8, hipMemcpyDeviceToDevice, st));
   int prec = o->prec;
   const int first = o->switch_from;
@@ -239,16 +248,21 @@ ffk_status pcg_solve(ffk_system* s, const ffk_precond* P, const double* F, doubl
     dot64(R, Z, n, PART, SC + rho, st);
     HIPCHK(hipMemcpyAsync(Pv, Z, n * 8, hipMemcpyDeviceToDevice, st));
   };
-  restart_direction();
+  if (o->resume && o->direction_dev) {
+    // the caller's direction, with rho = r^T P^-1 r of the true residual
+    apply_prec(R, Z);
+    dot64(R, Z, n, PART, SC + rho, st);
+    HIPCHK(hipMemcpyAsync(Pv, o->direction_dev, n * 8, hipMemcpyDeviceToDevice, st));
+  } else {
+    restart_direction();
+  }
 
   ffk_status status = FFK_NOT_CONVERGED;
-  double best_true = fnorm * fnorm;   // alpha = 0
   int64_t best_it = 0;   // iteration of the best true residual so far
-  double rel_upd = 1.0, rel_true = 1.0;
-  int64_t it = 0, n_ref = 0, n_esc = 0;
-  if (fnorm == 0.0) {
+  int64_t it = 0, n_esc = 0;
+  if (fnorm == 0.0 || (o->resume && rel_true <= o->tol)) {
     status = FFK_OK;
-    rel_upd = rel_true = 0.0;
+    if (fnorm == 0.0) rel_upd = rel_true = 0.0;
   }
   int64_t hist_len = 0;
   const int refresh = o->refresh_every;
@@ -405,6 +419,7 @@ ffk_status pcg_solve(ffk_system* s, const ffk_precond* P, const double* F, doubl
     ++n_ref;
     if (rel_true <= o->tol) status = FFK_OK;
   }
+  if (o->direction_dev) HIPCHK(hipMemcpyAsync(o->direction_dev, Pv, n * 8, hipMemcpyDeviceToDevice, st));
   HIPCHK(hipStreamSynchronize(st));
   const double total =
       std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();

@@ -36,7 +36,8 @@ class PcgOpts(ctypes.Structure):
                 ("prec", ctypes.c_int32), ("refresh_every", ctypes.c_int32), ("escalate", ctypes.c_int32),
                 ("flexible", ctypes.c_int32), ("timing", ctypes.c_int32), ("switch_below", ctypes.c_double),
                 ("progress_every", ctypes.c_int32), ("switch_from", ctypes.c_int32),
-                ("gap_escalate", ctypes.c_double)]
+                ("gap_escalate", ctypes.c_double), ("resume", ctypes.c_int32),
+                ("direction", ctypes.c_void_p)]
 
 
 class PcgReport(ctypes.Structure):
@@ -366,11 +367,18 @@ def pcg_solve(ctx: Context, sys: System, P: Precond | None, F: torch.Tensor, lam
               max_iter: int = 0, prec: int = FP64, refresh_every: int = 10, escalate: bool = True,
               flexible: bool = False, timing: bool = False, hist_cap: int = 0, alpha: torch.Tensor | None = None,
               switch_below: float = 0.0, progress_every: int = 0, switch_from: int = FP64,
-              gap_escalate: float = 0.0, stream=None):
+              gap_escalate: float = 0.0, resume: bool = False, direction: torch.Tensor | None = None,
+              stream=None):
+    """resume: start from the content of `alpha` (required then).  direction:
+    with resume, the search direction to continue along (None: restart);
+    in every case it receives the direction of the next iteration."""
     if alpha is None:
+        if resume:
+            raise ValueError("pcg_solve: resume needs the starting alpha")
         alpha = torch.empty(sys.n, dtype=torch.float64, device=ctx.torch_device)
     o = PcgOpts(lam, tol, max_iter, prec, refresh_every, int(escalate), int(flexible), int(timing), switch_below,
-                int(progress_every), int(switch_from), float(gap_escalate))
+                int(progress_every), int(switch_from), float(gap_escalate), int(resume),
+                _ptr(direction, torch.float64) if direction is not None else None)
     rep = PcgReport()
     hist = (ctypes.c_double * hist_cap)() if hist_cap > 0 else None
     if hist is not None:

@@ -7,6 +7,7 @@ labels of smaller systems of the same molecule.
     python -m paper_2212_12737_amd.study rot --config m21_n2000 [--sweep-N 250,500,1000]
     python -m paper_2212_12737_amd.study spectrum --config m21_n2000 [--spec-N 100 --spec-ks 100,400,1600]
     python -m paper_2212_12737_amd.study sym --config m21_n2000 [--sym-N 1000 --sym-orders 1,2,4,8]
+    python -m paper_2212_12737_amd.study long --config m60_n20000 --state-out DIR [--state-in PREV --deadline-s 1000]
 
 `labels` computes the exact labels (dense FP64 Cholesky on the GPU, about a
 minute per N = 2000 system) and saves one .npy per training system, so they
@@ -17,7 +18,9 @@ small systems, the power-law fit, and the workload solved at the predicted
 sizes and over a grid of k.  `spectrum` compares the spectrum of the
 preconditioned matrix across strategies and sizes with the optimal rank-k
 preconditioner (section 4.1), on a small system.  `sym` times the kernel
-symmetrized over groups of atom permutations (product and solve).  Every step of the solver
+symmetrized over groups of atom permutations (product and solve).  `long` runs
+the workload's solve in segments of one job each, resuming PCG from the saved
+alpha and search direction.  Every step of the solver
 runs in libffkrr; the dense eigen-analysis of `spectrum` runs on the host.
 """
 from __future__ import annotations
@@ -303,9 +306,121 @@ def symmetry(ctx, config, N, orders, reps):
     ffk.set_symmetries(ctx, S, transposition_group(S.M, 0))
 
 
+def _train_network(ctx, synth, cfg, train):
+    """The score network from exact labels of `systems` systems of N
+    geometries of the workload's molecule (displacement seeds disjoint from
+    the workload's), trained for `steps` steps, as the benchmark trains it."""
+    systems, N, steps = train
+    S_tr, y_tr = [], []
+    for t in range(systems):
+        _, S = _system(ctx, synth, cfg, N, cfg.disp_seed + 1000 + t)
+        S_tr.append(S)
+        y_tr.append(learned.make_labels(ctx, S, cfg.lam))
+    net, _ = learned.train(ctx, S_tr, y_tr, H=256, steps=steps, batch=256, lr=1e-3, seed=7,
+                           log_every=max(1, steps // 4))
+    return net
+
+
+def long_solve(ctx, config, state_in, state_out, deadline_s, chunk, progress, train, max_chunks=0):
+    """The workload's mixed-precision solve (learned columns, L stored FP32, the
+    benchmark's schedule) run in segments that each fit one job: every
+    segment rebuilds the system and the preconditioner from the saved column
+    indices, resumes PCG from the saved alpha and search direction (true
+    residual in FP64, direction kept), runs it in chunks of `chunk`
+    iterations until `deadline_s` seconds after the start, and saves alpha,
+    the direction and a log.  One JSON line per chunk and per segment."""
+    t_start = time.perf_counter()
+    synth, cfg = _config(config)
+    os.makedirs(state_out, exist_ok=True)
+    log_path = os.path.join(state_out, "log.json")
+    meta = {"config": config, "segments": []}
+    if state_in and os.path.exists(os.path.join(state_in, "log.json")):
+        with open(os.path.join(state_in, "log.json")) as f:
+            meta = json.load(f)
+    seg = {"segment": len(meta["segments"])}
+    s = synth.config_system(cfg)
+    dev = ctx.torch_device
+    S = ffk.descriptor_build(ctx, torch.as_tensor(s.R, device=dev), cfg.sigma)
+    F = torch.as_tensor(s.flat_forces(), device=dev)
+    torch.cuda.synchronize()
+    seg["t_system_s"] = time.perf_counter() - t_start
+    t0 = time.perf_counter()
+    idx_in = os.path.join(state_in, "idx.npy") if state_in else None
+    if idx_in and os.path.exists(idx_in):
+        idx = torch.as_tensor(np.load(idx_in), device=dev)
+        seg["selection"] = "saved"
+    else:
+        net = _train_network(ctx, synth, cfg, train) if cfg.strategy == "learned" else None
+        idx = learned.select(ctx, net, S, cfg.k, cfg.sel_seed) if net is not None else \
+            ffk.nystrom_select(ctx, S, cfg.strategy, cfg.k, lam=cfg.lam, seed=cfg.sel_seed)
+        seg["selection"] = cfg.strategy
+    torch.cuda.synchronize()
+    seg["t_select_s"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    P = ffk.precond_build(ctx, S, idx, cfg.lam, store=ffk.FP32, lowmem=True)
+    if P.k_eff < 0.95 * cfg.k and seg["selection"] != "saved":   # the rank collapsed: pivoted Cholesky
+        del P
+        idx = ffk.nystrom_select(ctx, S, "pivchol", cfg.k)
+        P = ffk.precond_build(ctx, S, idx, cfg.lam, store=ffk.FP32, lowmem=True)
+        seg["selection"] = "pivchol-fallback"
+    np.save(os.path.join(state_out, "idx.npy"), idx.cpu().numpy())
+    torch.cuda.synchronize()
+    seg["t_build_s"] = time.perf_counter() - t0
+    seg["k_eff"] = int(P.k_eff)
+    resume = bool(state_in) and os.path.exists(os.path.join(state_in, "alpha.npy"))
+    if resume:
+        alpha = torch.as_tensor(np.load(os.path.join(state_in, "alpha.npy")), device=dev)
+        direction = torch.as_tensor(np.load(os.path.join(state_in, "direction.npy")), device=dev)
+    else:
+        alpha = torch.zeros(S.n, dtype=torch.float64, device=dev)
+        direction = torch.empty(S.n, dtype=torch.float64, device=dev)
+    prec = meta.get("prec", ffk.BF16X3)
+    print(json.dumps({"segment_start": seg, "resume": resume}), flush=True)
+    seg.update({"iters": 0, "t_pcg_s": 0.0, "chunks": 0})
+    status, t_chunk = 1, 0.0
+    while time.perf_counter() - t_start + 1.3 * t_chunk + 10.0 < deadline_s and \
+            (max_chunks <= 0 or seg["chunks"] < max_chunks):
+        t0 = time.perf_counter()
+        alpha, rep = ffk.pcg_solve(ctx, S, P, F, cfg.lam, tol=1e-6, max_iter=chunk, prec=prec,
+                                   refresh_every=ffk.MIXED_REFRESH, escalate=True,
+                                   switch_below=ffk.MIXED_SWITCH_BELOW, switch_from=ffk.MIXED_SWITCH_FROM,
+                                   progress_every=progress, alpha=alpha, direction=direction, resume=resume)
+        torch.cuda.synchronize()
+        t_chunk = time.perf_counter() - t0
+        resume = True
+        if rep.n_escalations > 0:   # an escalation moved the products up the ladder: keep them there
+            prec = int(rep.final_prec)
+        status = int(rep.status)
+        seg["iters"] += int(rep.iters)
+        seg["t_pcg_s"] += t_chunk
+        seg["chunks"] += 1
+        seg["rel_res_true"] = rep.rel_res_true
+        print(json.dumps({"chunk": seg["chunks"], "iters": int(rep.iters), "seconds": t_chunk,
+                          "rel_res_true": rep.rel_res_true, "status": status, "final_prec": prec,
+                          "n_escalations": int(rep.n_escalations)}), flush=True)
+        if status != 1:   # converged, or an error: stop here
+            break
+    seg["status"] = status
+    seg["t_segment_s"] = time.perf_counter() - t_start
+    np.save(os.path.join(state_out, "alpha.npy"), alpha.cpu().numpy())
+    np.save(os.path.join(state_out, "direction.npy"), direction.cpu().numpy())
+    meta["segments"].append(seg)
+    meta["prec"] = prec
+    meta["iters_total"] = sum(g["iters"] for g in meta["segments"])
+    meta["t_pcg_total_s"] = sum(g["t_pcg_s"] for g in meta["segments"])
+    meta["t_total_s"] = sum(g["t_segment_s"] for g in meta["segments"])
+    meta["status"] = status
+    meta["rel_res_true"] = seg.get("rel_res_true")
+    with open(log_path, "w") as f:
+        json.dump(meta, f, indent=1)
+    print(json.dumps({"segment_done": seg, "iters_total": meta["iters_total"],
+                      "t_pcg_total_s": meta["t_pcg_total_s"], "t_total_s": meta["t_total_s"]}), flush=True)
+    return meta
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("mode", choices=["labels", "compare", "rot", "spectrum", "sym"])
+    ap.add_argument("mode", choices=["labels", "compare", "rot", "spectrum", "sym", "long"])
     ap.add_argument("--config", default="m21_n10000")
     ap.add_argument("--out", default="study_labels")
     ap.add_argument("--labels", default="study_labels")
@@ -321,6 +436,13 @@ def main(argv=None):
     ap.add_argument("--spec-out", default=None, help="spectrum: .npz with the dominant eigenvalues")
     ap.add_argument("--sym-N", type=int, default=1000, help="sym: geometries of the system")
     ap.add_argument("--sym-orders", default="1,2,4,8", help="sym: group orders (powers of two)")
+    ap.add_argument("--state-in", default=None, help="long: directory of the previous segment's state")
+    ap.add_argument("--state-out", default="long_state", help="long: directory for this segment's state")
+    ap.add_argument("--deadline-s", type=float, default=1000.0, help="long: seconds after start to stop by")
+    ap.add_argument("--chunk", type=int, default=2000, help="long: PCG iterations between resumes")
+    ap.add_argument("--progress", type=int, default=1000, help="long: PCG progress line every so many iterations")
+    ap.add_argument("--train", default="4,500,2000", help="long: network training systems, N each, steps")
+    ap.add_argument("--max-chunks", type=int, default=0, help="long: at most so many chunks (0: no limit)")
     a = ap.parse_args(argv)
     ctx = ffk.create(0)
     ints = lambda t: [int(x) for x in t.split(",")]
@@ -330,6 +452,9 @@ def main(argv=None):
         compare(ctx, a.config, a.labels, a.steps, (a.arms or "learned,pivchol,uniform,leverage").split(","))
     elif a.mode == "rot":
         rule_of_thumb(ctx, a.config, ints(a.sweep_N), ints(a.ks), ints(a.grid), (a.arms or "fp64,mixed").split(","))
+    elif a.mode == "long":
+        long_solve(ctx, a.config, a.state_in, a.state_out, a.deadline_s, a.chunk, a.progress, ints(a.train),
+                   a.max_chunks)
     elif a.mode == "sym":
         symmetry(ctx, a.config, a.sym_N, ints(a.sym_orders), 5)
     else:

@@ -497,6 +497,41 @@ def test_pcg_restarts_after_a_gap_escalation(ffk, ctx):
     assert rep.iters <= 200 and rep.n_escalations >= 1
 
 
+@pytest.mark.parametrize("prec", ["fp64", "bf16x3"])
+def test_pcg_resume_continues_the_solve(ffk, ctx, small, prec):
+    """A solve stopped halfway and resumed from (alpha, direction) continues
+    the same CG: the resume replaces r by the true residual, as a refresh does,
+    and keeps the direction, so the two parts together take about the
+    iterations of the uninterrupted solve.  A resume without the direction
+    (a restart from p = P^-1 r) converges too.  Checked against the oracle's
+    dense residual."""
+    cfg, s, S, K, idx = small
+    P = ffk.precond_build(ctx, S, idx, cfg.lam, store=ffk.FP32)
+    F = s.flat_forces()
+    Fd = dev(F)
+    kw = dict(tol=1e-8, prec=ffk.PRECISIONS[prec], refresh_every=10, escalate=True,
+              switch_below=0.7 if prec != "fp64" else 0.0, switch_from=ffk.FP32 if prec != "fp64" else ffk.FP64)
+    _, full = ffk.pcg_solve(ctx, S, P, Fd, cfg.lam, max_iter=20000, **kw)
+    assert full.status == 0
+    half = max(2, full.iters // 2)
+    a = torch.empty_like(Fd)
+    d = torch.empty_like(Fd)
+    a, r1 = ffk.pcg_solve(ctx, S, P, Fd, cfg.lam, max_iter=half, alpha=a, direction=d, **kw)
+    assert r1.status != 0 and r1.iters == half
+    a2, r2 = ffk.pcg_solve(ctx, S, P, Fd, cfg.lam, max_iter=20000, alpha=a.clone(), direction=d.clone(),
+                           resume=True, **kw)
+    a3, r3 = ffk.pcg_solve(ctx, S, P, Fd, cfg.lam, max_iter=20000, alpha=a.clone(), resume=True, **kw)
+    print("%s: uninterrupted %d iterations; %d + %d resumed with the direction; %d + %d restarted"
+          % (prec, full.iters, r1.iters, r2.iters, r1.iters, r3.iters), flush=True)
+    assert r2.status == 0 and r3.status == 0
+    assert r1.iters + r2.iters <= full.iters + max(3, full.iters // 20)
+    for x in (a2, a3):
+        assert oracle_relres(K, cfg.lam, host(x), F) <= 1.01e-8
+    # a converged alpha resumes to an immediate stop
+    _, r4 = ffk.pcg_solve(ctx, S, P, Fd, cfg.lam, alpha=a2.clone(), resume=True, **kw)
+    assert r4.status == 0 and r4.iters == 0
+
+
 def test_pcg_rejects_reduced_first_phase(ffk, ctx, small):
     cfg, s, S, K, idx = small
     P = ffk.precond_build(ctx, S, idx, cfg.lam, store=ffk.FP32)
