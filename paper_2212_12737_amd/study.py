@@ -316,6 +316,7 @@ def _train_network(ctx, synth, cfg, train):
         _, S = _system(ctx, synth, cfg, N, cfg.disp_seed + 1000 + t)
         S_tr.append(S)
         y_tr.append(learned.make_labels(ctx, S, cfg.lam))
+        print(json.dumps({"training_system": t, "N": N, "labels": "exact ridge leverage"}), flush=True)
     net, _ = learned.train(ctx, S_tr, y_tr, H=256, steps=steps, batch=256, lr=1e-3, seed=7,
                            log_every=max(1, steps // 4))
     return net
@@ -356,6 +357,7 @@ def long_solve(ctx, config, state_in, state_out, deadline_s, chunk, progress, tr
         seg["selection"] = cfg.strategy
     torch.cuda.synchronize()
     seg["t_select_s"] = time.perf_counter() - t0
+    print(json.dumps({"selected": seg["selection"], "seconds": seg["t_select_s"]}), flush=True)
     t0 = time.perf_counter()
     P = ffk.precond_build(ctx, S, idx, cfg.lam, store=ffk.FP32, lowmem=True)
     if P.k_eff < 0.95 * cfg.k and seg["selection"] != "saved":   # the rank collapsed: pivoted Cholesky
