@@ -85,7 +85,26 @@ __global__ __launch_bounds__(256) void k_jv_tile(const double* __restrict__ R, c
       ug[gl] = u;
     }
     cpart[(int64_t)blockIdx.x * D + d] = cs;
-    if (UT) {   // transposed copy: ng consecutive geometries of row d
+    if (UT && MODE >= 2 && ng == GT) {
+      // transposed split-BF16 copy of a full group: the GT geometries of row
+      // d are consecutive K indices (four at a time in the interleaved
+      // layout), written as 8-byte vectors instead of 2-byte stores
+#pragma unroll
+      for (int q4 = 0; q4 < GT; q4 += 4) {
+        uint32_t h[2], l[2];
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+          const float f0 = (float)ug[q4 + 2 * e], f1 = (float)ug[q4 + 2 * e + 1];
+          const bf16_t h0 = f2bf(f0), h1 = f2bf(f1);
+          h[e] = (uint32_t)h0 | ((uint32_t)h1 << 16);
+          l[e] = (uint32_t)f2bf(f0 - bf2f(h0)) | ((uint32_t)f2bf(f1 - bf2f(h1)) << 16);
+        }
+        const int64_t g = g0 + q4;   // a multiple of 4
+        const int64_t of = frag_off(d, MODE == 3 ? 8 * (g >> 2) : g, ldut / 32);
+        *reinterpret_cast<uint2*>(static_cast<bf16_t*>(UT) + of) = make_uint2(h[0], h[1]);
+        *reinterpret_cast<uint2*>(static_cast<bf16_t*>(UTl) + of) = make_uint2(l[0], l[1]);
+      }
+    } else if (UT) {   // transposed copy: ng consecutive geometries of row d
 #pragma unroll
       for (int gl = 0; gl < GT; ++gl)
         if (gl < ng) {
@@ -164,42 +183,61 @@ __device__ inline double block_sum_waves(double x) {
   return t;
 }
 
-// y_g = J_g^T G_g + shift v_g, one geometry per block (thread per atom).
+// y_g = J_g^T G_g + shift v_g, one geometry per block.
 // y = J^T G + shift v for geometry g from its coordinates sR (3M) and its
 // row sG (D) of G, both in LDS.  With vy_part (and v), also v_g . y_g into
 // vy_part[g]: the block partials of v^T y, which CG needs as p^T q.
+// Each atom takes a group of L lanes (a power of two, within a wave, as many
+// as the block holds for all M atoms): lane `part` sums the partners b =
+// part, part + L, ..., and the group's sums meet in a fixed butterfly, so
+// the result does not depend on timing.  (One lane per atom left most of the
+// block idle behind a serial loop over M - 1 partners.)
 __device__ inline void jtg_atoms(const double* sR, const double* sG, int64_t g, int M, const double* v,
                                  double shift, double* y, bool accumulate = false, double* vy_part = nullptr) {
+  int L = 1;
+  while (L < 64 && 2 * L * M <= (int)blockDim.x) L *= 2;
+  const int part = (int)threadIdx.x & (L - 1);
+  const int per = (int)blockDim.x / L;   // atoms per pass
   double vy = 0.0;
-  for (int a = threadIdx.x; a < M; a += blockDim.x) {
+  for (int a0 = 0; a0 < M; a0 += per) {   // uniform across the block
+    const int a = a0 + (int)threadIdx.x / L;
     double ax = 0.0, ay = 0.0, az = 0.0;
-    const double xa = sR[3 * a], ya = sR[3 * a + 1], za = sR[3 * a + 2];
-    for (int b = 0; b < M; ++b) {
-      if (b == a) continue;
-      const int idx = a > b ? a * (a - 1) / 2 + b : b * (b - 1) / 2 + a;
-      const double dx = xa - sR[3 * b], dy = ya - sR[3 * b + 1], dz = za - sR[3 * b + 2];
-      const double ir = 1.0 / sqrt(dx * dx + dy * dy + dz * dz);
-      const double c = sG[idx] * ir * ir * ir;
-      ax -= c * dx;
-      ay -= c * dy;
-      az -= c * dz;
+    if (a < M) {
+      const double xa = sR[3 * a], ya = sR[3 * a + 1], za = sR[3 * a + 2];
+      for (int b = part; b < M; b += L) {
+        if (b == a) continue;
+        const int idx = a > b ? a * (a - 1) / 2 + b : b * (b - 1) / 2 + a;
+        const double dx = xa - sR[3 * b], dy = ya - sR[3 * b + 1], dz = za - sR[3 * b + 2];
+        const double ir = 1.0 / sqrt(dx * dx + dy * dy + dz * dz);
+        const double c = sG[idx] * ir * ir * ir;
+        ax -= c * dx;
+        ay -= c * dy;
+        az -= c * dz;
+      }
     }
-    const int64_t o = g * 3 * M + 3 * a;
-    if (v) {
-      ax += shift * v[o];
-      ay += shift * v[o + 1];
-      az += shift * v[o + 2];
+    for (int o = L / 2; o >= 1; o >>= 1) {
+      ax += __shfl_xor(ax, o);
+      ay += __shfl_xor(ay, o);
+      az += __shfl_xor(az, o);
     }
-    if (accumulate) {
-      y[o] += ax;
-      y[o + 1] += ay;
-      y[o + 2] += az;
-    } else {
-      y[o] = ax;
-      y[o + 1] = ay;
-      y[o + 2] = az;
+    if (a < M && part == 0) {
+      const int64_t o = g * 3 * M + 3 * a;
+      if (v) {
+        ax += shift * v[o];
+        ay += shift * v[o + 1];
+        az += shift * v[o + 2];
+      }
+      if (accumulate) {
+        y[o] += ax;
+        y[o + 1] += ay;
+        y[o + 2] += az;
+      } else {
+        y[o] = ax;
+        y[o + 1] = ay;
+        y[o + 2] = az;
+      }
+      if (vy_part) vy += (ax * v[o] + ay * v[o + 1]) + az * v[o + 2];
     }
-    if (vy_part) vy += (ax * v[o] + ay * v[o + 1]) + az * v[o + 2];
   }
   if (vy_part) {   // uniform across the block
     const double t = block_sum_waves(vy);
