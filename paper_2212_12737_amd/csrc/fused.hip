@@ -1,4 +1,5 @@
-// Fused kernel product for short descriptors (D <= 128) in BF16 and split BF16.
+// Fused kernel product for short descriptors in BF16 and split BF16 (where it
+// was measured faster: D <= 96, and D <= 128 up to N_t N_s = 4096^2).
 //
 // The product's two dense steps (the block structure of Sec. 2.1 rewritten
 // over geometry pairs, see mvm.hip):
@@ -26,16 +27,16 @@
 // [U^T | X_c^T], the coefficients in blocks laid out for this kernel (dA hi
 // and lo, B: each lane's 16 bytes where its MFMA operands want them) and pd;
 // every LDS read is a 16-byte vector at 16 x lane (read as double2, pd made
-// the compiler wait for all DMA in flight before it).  A stage is 34 KB at
-// D = 128 (four stages), 22 KB at D = 64 (six).
+// the compiler wait for all DMA in flight before it).  Three stages; a stage
+// is 34 KB at D = 128.
 //
 // Where it pays: the two-GEMM form moves about 16 bytes per geometry pair
 // (B, dA, -W written and read) plus its operand panels; the fused form moves
 // the 8 bytes of B and dA plus the chunk operands once per 64 targets, which
-// grows with D (about 41 bytes per pair at D = 210).  Measured on MI355X at
-// N = 2000, split BF16 product: D = 36, 66, 120: 39, 44, 53 us fused against
-// 53, 58, 62 us; D = 210: 76 against 71 us, and at N = 10000 1159 against
-// 790 us.  Hence D <= 128 only.
+// grows with D (about 41 bytes per pair at D = 210).  Measured on MI355X,
+// split BF16 product, fused against two GEMMs: N = 2000, D = 36, 66, 120:
+// 37, 45, 54 us against 54, 58, 61; N = 10000: D = 36 331 against 611 us,
+// D = 120 733 against 676, D = 210 1159 against 790.
 // Each workgroup writes its partial G rows and row sums of W; the
 // split-K reduction and J^T G follow in k_jtg_reduce, as after GEMM 2.
 #include "gemm.hpp"
