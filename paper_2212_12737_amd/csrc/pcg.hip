@@ -228,10 +228,12 @@ ffk_status pcg_solve(ffk_system* s, const ffk_precond* P, const double* F, doubl
   double best_true = fnorm * fnorm;   // alpha = 0
   double rel_upd = 1.0, rel_true = 1.0;
   int64_t n_ref = 0;
-  if (o->resume) {
+  const bool resume = o->resume && fnorm > 0.0;   // F = 0: the solution is alpha = 0 either way
+  if (resume) {
     // continue from the caller's alpha: the true residual replaces r, as at a refresh
-    rel_true = rel_upd = fnorm > 0.0 ? sqrt(best_true = true_residual()) / fnorm : 0.0;
+    best_true = true_residual();
     ++n_ref;
+    rel_true = rel_upd = sqrt(best_true) / fnorm;
   } else {
     HIPCHK(hipMemsetAsync(alpha, 0, n * 8, st));
     HIPCHK(hipMemcpyAsync(R, F, n * 8, hipMemcpyDeviceToDevice, st));
@@ -248,7 +250,7 @@ ffk_status pcg_solve(ffk_system* s, const ffk_precond* P, const double* F, doubl
     dot64(R, Z, n, PART, SC + rho, st);
     HIPCHK(hipMemcpyAsync(Pv, Z, n * 8, hipMemcpyDeviceToDevice, st));
   };
-  if (o->resume && o->direction_dev) {
+  if (resume && o->direction_dev) {
     // the caller's direction, with rho = r^T P^-1 r of the true residual
     apply_prec(R, Z);
     dot64(R, Z, n, PART, SC + rho, st);
@@ -260,7 +262,7 @@ ffk_status pcg_solve(ffk_system* s, const ffk_precond* P, const double* F, doubl
   ffk_status status = FFK_NOT_CONVERGED;
   int64_t best_it = 0;   // iteration of the best true residual so far
   int64_t it = 0, n_esc = 0;
-  if (fnorm == 0.0 || (o->resume && rel_true <= o->tol)) {
+  if (fnorm == 0.0 || (resume && rel_true <= o->tol)) {
     status = FFK_OK;
     if (fnorm == 0.0) rel_upd = rel_true = 0.0;
   }

@@ -112,4 +112,13 @@ def test_solve_arguments_and_zero_forces(ffk, ctx, small):
         a, rep = ffk.pcg_solve(ctx, S, P, Z, 1e-6, prec=prec, switch_below=sw)
         assert rep.status == 0 and rep.iters == 0
         assert torch.count_nonzero(a).item() == 0
+    # resuming a solve of F = 0 from a nonzero alpha returns alpha = 0 as well
+    a0 = torch.ones_like(F)
+    a, rep = ffk.pcg_solve(ctx, S, P, Z, 1e-6, alpha=a0, direction=torch.ones_like(F), resume=True)
+    assert rep.status == 0 and rep.iters == 0 and torch.count_nonzero(a).item() == 0
+    # resume needs the starting alpha; the direction may not alias F or alpha
+    with pytest.raises(ValueError):
+        ffk.pcg_solve(ctx, S, P, F, 1e-6, resume=True)
+    with pytest.raises(ffk.FfkError):
+        ffk.pcg_solve(ctx, S, P, F, 1e-6, alpha=torch.zeros_like(F), direction=F, resume=True)
     still_works(ffk, ctx, s, S)
