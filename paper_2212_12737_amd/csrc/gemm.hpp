@@ -60,6 +60,7 @@ struct FragCoord {
   bool f64;             // FP64 MFMA output layout
   int tn;               // tile column index (n0 / BN)
   int wcol, nwcol;      // this wave's column index among the block's wave columns
+  int split;            // K-split index of the block (which partial it writes)
   __device__ inline int row(int tm, int v) const {
     return wm0 + tm * 16 + (f64 ? 4 * v + (lane >> 4) : 4 * (lane >> 4) + v);
   }
@@ -187,7 +188,7 @@ __global__ __launch_bounds__(256) void gemm_scalar_kernel(ScalarArgs<TI> g, Epi 
     if (t + 1 < te) store(buf ^ 1);
     __syncthreads();
   }
-  FragCoord fc{m0 + wm0, n0 + wn0, lane, m0, n0, sizeof(T) == 8, (int)blockIdx.x, wave & 1, 2};
+  FragCoord fc{m0 + wm0, n0 + wn0, lane, m0, n0, sizeof(T) == 8, (int)blockIdx.x, wave & 1, 2, (int)blockIdx.z};
   epi.template run<T, TM, TN>(acc, fc, reinterpret_cast<char*>(&As[0][0][0]));
 }
 
@@ -310,7 +311,7 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(Bf16Args g, Epi epi) {
       __syncthreads();
     }
   }
-  FragCoord fc{m0 + wm0, n0 + wn0, lane, m0, n0, false, (int)blockIdx.x, wave & 1, 2};
+  FragCoord fc{m0 + wm0, n0 + wn0, lane, m0, n0, false, (int)blockIdx.x, wave & 1, 2, (int)blockIdx.z};
   epi.template run<float, TM, TN>(acc, fc, reinterpret_cast<char*>(&As[0][0]));
 }
 
@@ -334,14 +335,34 @@ __device__ inline void dma16(const void* g, void* lds_base) {
                                    (void __attribute__((address_space(3)))*)lds_base, 16, 0, 0);
 }
 
-// XCD-aware tile order: consecutive dispatch slots go to different XCDs
-// (round robin over 8); remap so each XCD works on a contiguous range of tiles,
-// grouped by 8 tile rows, so tiles that share operand rows share an L2.
-__device__ inline void tile_coords(int& tm, int& tn) {
+// XCD-aware tile order.  Workgroup w of the grid (x fastest, then y, then z)
+// runs on XCD w % 8 as that XCD's (w / 8)-th.  ALL: each XCD gets a
+// contiguous range of all (K split, tile) items, whatever their count (the
+// tiles of one row of a 79 x 7 grid had gone to seven L2s: split BF16 at M =
+// 60, N = 20000, GEMM 1 3.78 -> 3.66 ms and GEMM 2 6.09 -> 5.94 ms; 6% at M =
+// 42, N = 5000).  Otherwise the split is blockIdx.z and the tiles of a split
+// are remapped only when their count is a multiple of 8 (the FP32 GEMM 2 on
+// 128 x 128 tiles, 14 x 158 x splits, measured 17% slower with the general
+// remap).  Within a
+// split, tiles are grouped by 8 tile rows, so tiles that run together on an
+// XCD share operand rows in its L2.
+template <bool ALL>
+__device__ inline void tile_coords(int& tm, int& tn, int& tz) {
   const int nt_n = gridDim.x, nt_m = gridDim.y;
   const int T = nt_m * nt_n;
-  int lin = blockIdx.y * nt_n + blockIdx.x;
-  if (T % 8 == 0) lin = (lin % 8) * (T / 8) + lin / 8;
+  int lin;
+  if constexpr (ALL) {
+    const int W = T * (int)gridDim.z;
+    const int w = ((int)blockIdx.z * nt_m + (int)blockIdx.y) * nt_n + (int)blockIdx.x;
+    const int xcd = w % 8, idx = w / 8, q = W / 8, r = W % 8;
+    const int L = (xcd < r ? xcd * (q + 1) : r * (q + 1) + (xcd - r) * q) + idx;
+    tz = L / T;
+    lin = L % T;
+  } else {
+    tz = (int)blockIdx.z;
+    lin = (int)blockIdx.y * nt_n + (int)blockIdx.x;
+    if (T % 8 == 0) lin = (lin % 8) * (T / 8) + lin / 8;
+  }
   const int G = 8;
   const int per_group = G * nt_n;
   const int grp = lin / per_group;
@@ -429,16 +450,21 @@ __global__ __launch_bounds__(TL::NT) void gemm_dma_kernel(DmaArgs g, Epi epi) {
   typedef typename DmaMfma<T>::acc_t acc_t;
   __shared__ __attribute__((aligned(1024))) char smem[S * STAGE_BYTES];
 
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  int tmi, tni;
-  tile_coords(tmi, tni);
+  // BF16 operands: the wave index in a scalar register, so every operand
+  // address is a scalar base plus the lane's offset (228 rather than 252
+  // VGPRs on the split 256 x 256 tile).  The FP32 and FP64 loops are left as
+  // they were measured.
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = sizeof(T) == 2 ? __builtin_amdgcn_readfirstlane(tid >> 6) : tid >> 6;
+  int tmi, tni, tzi;
+  tile_coords<X3 && TM * TN >= 32>(tmi, tni, tzi);
   if (g.lower_only && tni > tmi) return;
   const int m0 = tmi * BM, n0 = tni * BN;
   const int wm = wave / WN, wn = wave % WN;
   const int t0 = g.seg[0].K / BK;
   const int T_ = t0 + (g.nseg > 1 ? g.seg[1].K / BK : 0);
-  const int tb = (int)((int64_t)T_ * blockIdx.z / gridDim.z);
-  const int te = (int)((int64_t)T_ * (blockIdx.z + 1) / gridDim.z);
+  const int tb = (int)((int64_t)T_ * tzi / gridDim.z);
+  const int te = (int)((int64_t)T_ * (tzi + 1) / gridDim.z);
 
   acc_t acc[TM][TN];
 #pragma unroll
@@ -581,7 +607,7 @@ __global__ __launch_bounds__(TL::NT) void gemm_dma_kernel(DmaArgs g, Epi epi) {
     }
   }
   __syncthreads();
-  FragCoord fc{m0 + wm * (BM / WM), n0 + wn * (BN / WN), lane, m0, n0, sizeof(T) == 8, tni, wn, WN};
+  FragCoord fc{m0 + wm * (BM / WM), n0 + wn * (BN / WN), lane, m0, n0, sizeof(T) == 8, tni, wn, WN, tzi};
   epi.template run<typename DmaMfma<T>::scalar_t, TM, TN>(acc, fc, smem);
 }
 
@@ -621,7 +647,7 @@ template <typename PT> struct EpiPart {
   int rows, cols;
   template <typename T, int TM, int TN, class Acc>
   __device__ void run(const Acc (&acc)[TM][TN], const FragCoord& f, char*) const {
-    PT* base = part + (int64_t)blockIdx.z * rows * ldp;
+    PT* base = part + (int64_t)f.split * rows * ldp;
 #pragma unroll
     for (int i = 0; i < TM; ++i)
 #pragma unroll
