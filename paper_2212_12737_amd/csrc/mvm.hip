@@ -183,17 +183,29 @@ __device__ inline double block_sum_waves(double x) {
   return t;
 }
 
+// Whether a geometry's descriptor row is staged in LDS beside its coordinates
+// and its row of G: while the block needs at most 20 KB, so that eight
+// blocks of four waves still share a CU (M up to about 50).  The J^T G
+// kernels wait on their loads: at M = 42, N = 5000 the staged row took the
+// reduce from 61.8 to 57.1 us; at M = 60, N = 20000 (29.8 KB, five blocks
+// per CU) it took it from 344 to 428 us.
+static inline bool jtg_stage_x(int M, int64_t D) { return (3 * M + 2 * D) * (int64_t)sizeof(double) <= 20480; }
+
 // y_g = J_g^T G_g + shift v_g, one geometry per block.
 // y = J^T G + shift v for geometry g from its coordinates sR (3M) and its
 // row sG (D) of G, both in LDS.  With vy_part (and v), also v_g . y_g into
-// vy_part[g]: the block partials of v^T y, which CG needs as p^T q.
+// vy_part[g]: the block partials of v^T y, which CG needs as p^T q.  The
+// inverse distance of a pair is its descriptor entry: given sX (the
+// geometry's descriptor row in LDS) it is read rather than recomputed with
+// an FP64 square root and divide per pair.
 // Each atom takes a group of L lanes (a power of two, within a wave, as many
 // as the block holds for all M atoms): lane `part` sums the partners b =
 // part, part + L, ..., and the group's sums meet in a fixed butterfly, so
 // the result does not depend on timing.  (One lane per atom left most of the
 // block idle behind a serial loop over M - 1 partners.)
-__device__ inline void jtg_atoms(const double* sR, const double* sG, int64_t g, int M, const double* v,
-                                 double shift, double* y, bool accumulate = false, double* vy_part = nullptr) {
+__device__ inline void jtg_atoms(const double* sR, const double* sG, const double* sX, int64_t g, int M,
+                                 const double* v, double shift, double* y, bool accumulate = false,
+                                 double* vy_part = nullptr) {
   int L = 1;
   while (L < 64 && 2 * L * M <= (int)blockDim.x) L *= 2;
   const int part = (int)threadIdx.x & (L - 1);
@@ -208,7 +220,7 @@ __device__ inline void jtg_atoms(const double* sR, const double* sG, int64_t g, 
         if (b == a) continue;
         const int idx = a > b ? a * (a - 1) / 2 + b : b * (b - 1) / 2 + a;
         const double dx = xa - sR[3 * b], dy = ya - sR[3 * b + 1], dz = za - sR[3 * b + 2];
-        const double ir = 1.0 / sqrt(dx * dx + dy * dy + dz * dz);
+        const double ir = sX ? sX[idx] : 1.0 / sqrt(dx * dx + dy * dy + dz * dz);
         const double c = sG[idx] * ir * ir * ir;
         ax -= c * dx;
         ay -= c * dy;
@@ -245,18 +257,24 @@ __device__ inline void jtg_atoms(const double* sR, const double* sG, int64_t g, 
   }
 }
 
-// y = J^T G + shift v, or y += J^T G with accumulate (then v is unused)
-__global__ void k_jtg(const double* __restrict__ R, const double* __restrict__ G,
+// y = J^T G + shift v, or y += J^T G with accumulate (then v is unused).
+// X: the uncentred descriptor rows, staged in LDS after G when given.
+__global__ void k_jtg(const double* __restrict__ R, const double* __restrict__ G, const double* __restrict__ X,
                       const double* __restrict__ v, double shift, int M, int64_t D,
                       double* __restrict__ y, int accumulate = 0, double* __restrict__ vy_part = nullptr) {
   extern __shared__ double sm[];
   double* sR = sm;
   double* sG = sm + 3 * M;
+  double* sX = X ? sG + D : nullptr;
   const int64_t g = blockIdx.x;
   for (int i = threadIdx.x; i < 3 * M; i += blockDim.x) sR[i] = R[g * 3 * M + i];
-  for (int64_t i = threadIdx.x; i < D; i += blockDim.x) sG[i] = G[g * D + i];
+  for (int64_t i = threadIdx.x; i < D; i += blockDim.x) {
+    sG[i] = G[g * D + i];
+    if (X) sX[i] = X[g * D + i];
+  }
   __syncthreads();
-  jtg_atoms(sR, sG, g, M, accumulate ? nullptr : v, shift, y, accumulate != 0, accumulate ? nullptr : vy_part);
+  jtg_atoms(sR, sG, sX, g, M, accumulate ? nullptr : v, shift, y, accumulate != 0,
+            accumulate ? nullptr : vy_part);
 }
 
 // Sum of the n partials p[0..n) by the calling wave: lane l adds l, l + 64,
@@ -272,14 +290,17 @@ __device__ inline double wave_sum_parts(const double* __restrict__ p, int n) {
 // The split-K reduction of GEMM 2 fused with J^T G: one block per geometry
 // forms its row of G = sum_z part_z + a0 s + w Xt in LDS (the arithmetic and
 // order of k_g_reduce) and applies J^T to it; G never goes to HBM.
+// With xmean, the descriptor row x = x_c + mean is staged after G in LDS.
 template <typename PT>
 __global__ void k_jtg_reduce(const PT* __restrict__ part, int splits, int64_t rows, const double* __restrict__ s,
-                             const double* __restrict__ Xt, const double* __restrict__ wpart, int ntn, double a0,
+                             const double* __restrict__ Xt, const double* __restrict__ xmean,
+                             const double* __restrict__ wpart, int ntn, double a0,
                              const double* __restrict__ R, const double* __restrict__ v, double shift, int M,
                              int64_t D, double* __restrict__ y, double* __restrict__ vy_part) {
   extern __shared__ double sm[];
   double* sR = sm;
   double* sG = sm + 3 * M;
+  double* sX = xmean ? sG + D : nullptr;
   __shared__ double wsh;
   const int64_t g = blockIdx.x;
   if (threadIdx.x < 64) {
@@ -293,10 +314,12 @@ __global__ void k_jtg_reduce(const PT* __restrict__ part, int splits, int64_t ro
     double acc = 0.0;
 #pragma unroll 4
     for (int z = 0; z < splits; ++z) acc += (double)part[((int64_t)z * rows + g) * D + c];
-    sG[c] = acc + a0 * s[c] + w * Xt[g * D + c];
+    const double xc = Xt[g * D + c];
+    sG[c] = acc + a0 * s[c] + w * xc;
+    if (xmean) sX[c] = xc + xmean[c];
   }
   __syncthreads();
-  jtg_atoms(sR, sG, g, M, v, shift, y, false, vy_part);
+  jtg_atoms(sR, sG, sX, g, M, v, shift, y, false, vy_part);
 }
 
 // ------------------------------------------------------------- epilogues ----
@@ -881,22 +904,25 @@ static void kernel_mvm_core(ffk_system* t, ffk_system* src, CoeffSet* coef, cons
   }
   mark(ev, 4, st);
   const int tb = M <= 64 ? 64 : 128;
-  const size_t shj = (3 * M + D) * sizeof(double);
+  const bool stage = jtg_stage_x(M, D);
+  const size_t shj = (3 * M + (stage ? 2 : 1) * D) * sizeof(double);
+  const double* xm = stage ? t->xmean.as<double>() : nullptr;
   clk_begin(CLK_JTG, st);
   if (go.splits < 0)
     k_jtg_reduce<float><<<N, 256, shj, st>>>(static_cast<const float*>(b.part), -go.splits, N, b.s,
-                                            t->Xc.as<double>(), b.wpart, go.ntn, t->a0, t->R.as<double>(), v,
-                                            shift, M, D, y, vy_part);
+                                            t->Xc.as<double>(), xm, b.wpart, go.ntn, t->a0, t->R.as<double>(),
+                                            v, shift, M, D, y, vy_part);
   else if (go.splits == 1)
-    k_jtg<<<N, tb, shj, st>>>(t->R.as<double>(), b.G, v, shift, M, D, y, 0, vy_part);
+    k_jtg<<<N, tb, shj, st>>>(t->R.as<double>(), b.G, stage ? t->X.as<double>() : nullptr, v, shift, M, D, y, 0,
+                              vy_part);
   else if (prec == FFK_FP64)
     k_jtg_reduce<double><<<N, 256, shj, st>>>(static_cast<const double*>(b.part), go.splits, N, b.s,
-                                             t->Xc.as<double>(), b.wpart, go.ntn, t->a0, t->R.as<double>(), v,
-                                             shift, M, D, y, vy_part);
+                                             t->Xc.as<double>(), xm, b.wpart, go.ntn, t->a0, t->R.as<double>(),
+                                             v, shift, M, D, y, vy_part);
   else
     k_jtg_reduce<float><<<N, 256, shj, st>>>(static_cast<const float*>(b.part), go.splits, N, b.s,
-                                            t->Xc.as<double>(), b.wpart, go.ntn, t->a0, t->R.as<double>(), v,
-                                            shift, M, D, y, vy_part);
+                                            t->Xc.as<double>(), xm, b.wpart, go.ntn, t->a0, t->R.as<double>(),
+                                            v, shift, M, D, y, vy_part);
   LAUNCHCHK();
   clk_end(CLK_JTG, st);
   mark(ev, 5, st);
@@ -1147,8 +1173,10 @@ void rect_mvm(const ffk_system* tr, const ffk_system* te, const double* alpha, d
   mvm_gemms_scalar<double>(a, c.Xt.as<double>(), tr->Xc.as<double>(), c.U.as<double>(), c.dA.as<double>(),
                            c.B.as<double>(), c.Wn.as<double>(), st, nullptr);
   const int tb = M <= 64 ? 64 : 128;
-  k_jtg<<<Nt, tb, (3 * M + D) * sizeof(double), st>>>(te->R.as<double>(), c.G.as<double>(), shift_v, shift, M, D,
-                                                      F, accumulate ? 1 : 0);
+  const bool stage = jtg_stage_x(M, D);
+  k_jtg<<<Nt, tb, (3 * M + (stage ? 2 : 1) * D) * sizeof(double), st>>>(
+      te->R.as<double>(), c.G.as<double>(), stage ? te->X.as<double>() : nullptr, shift_v, shift, M, D, F,
+      accumulate ? 1 : 0);
   LAUNCHCHK();
   if (!cache) HIPCHK(hipStreamSynchronize(st));   // the temporaries are freed on return
 }
