@@ -334,8 +334,21 @@ struct EpiW {
   template <typename T, int TM, int TN, class Acc>
   __device__ void run(const Acc (&acc)[TM][TN], const FragCoord& f, char* smem) const {
     double* red = reinterpret_cast<double*>(smem);   // [wave columns][BM]
+    // Loads go out in batches ahead of the stores (a load of B may not move
+    // above a store of -W, which it could alias): pd for all columns, then B
+    // for one block row at a time.  Indices are clamped to valid entries, so
+    // every load is in bounds; only valid entries are used and stored.
+    double pdv[TN];
 #pragma unroll
-    for (int i = 0; i < TM; ++i)
+    for (int j = 0; j < TN; ++j) pdv[j] = pd[min(f.col(j), Nc - 1)];
+#pragma unroll
+    for (int i = 0; i < TM; ++i) {
+      double bv[4][TN];
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+          bv[v][j] = (double)Bc[(int64_t)min(f.row(i, v), Nr - 1) * ldb + min(f.col(j), Nc - 1)];
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int r = f.row(i, v);
@@ -344,7 +357,7 @@ struct EpiW {
         for (int j = 0; j < TN; ++j) {
           const int c = f.col(j);
           if (r < Nr && c < Nc) {
-            const double w = (double)Bc[(int64_t)r * ldb + c] * ((double)acc[i][j][v] - pd[c]);
+            const double w = bv[v][j] * ((double)acc[i][j][v] - pdv[j]);
             Wn[(int64_t)r * ldw + c] = (CT)(-w);
             rs += w;
           }
@@ -355,6 +368,7 @@ struct EpiW {
         rs += __shfl_xor(rs, 8);
         if ((f.lane & 15) == 0) red[f.wcol * BM + (r - f.m0)] = rs;
       }
+    }
     __syncthreads();
     for (int t = threadIdx.x; t < BM; t += blockDim.x) {
       const int r = f.m0 + t;
@@ -393,20 +407,47 @@ struct EpiWT {
     double rs[TN];
 #pragma unroll
     for (int j = 0; j < TN; ++j) rs[j] = 0.0;
+    // BATCH: loads are issued in batches ahead of the stores they would
+    // otherwise follow.  The compiler may not move a load of B above a store
+    // of -W (they could alias), so loads written inside the loop each waited
+    // a full memory round trip (48 per tile of the split 256 x 256 tile).
+    // pd for all rows at once (pd has the padded length and is zero past the
+    // sources, so every load is in bounds), then the B vectors of one row at
+    // a time.  Not on the 4 x 4-block wave tiles of single BF16 and FP32:
+    // there the batch's registers would cost single BF16 its second
+    // workgroup per CU (115 -> 144 VGPRs; GEMM 1 at M = 60, N = 20000 1.66 ->
+    // 2.01 ms), whose main loop hides this epilogue, and FP32 gained nothing.
+    constexpr bool BATCH = X3 || TM * TN <= 4;
+    MT p[TM][4];
+    if constexpr (BATCH) {
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int c = f.row(i, 0) + v;
+          const double pv = pd[c];
+          p[i][v] = c < Ns ? (MT)pv : (MT)0;
+        }
+    }
 #pragma unroll
     for (int i = 0; i < TM; ++i) {
       const int c0 = f.row(i, 0);
-      MT p[4];
+      f4 bq[TN];
+      if constexpr (BATCH) {
 #pragma unroll
-      for (int v = 0; v < 4; ++v) p[v] = c0 + v < Ns ? (MT)pd[c0 + v] : (MT)0;
+        for (int j = 0; j < TN; ++j) bq[j] = *reinterpret_cast<const f4*>(Bc + (int64_t)f.col(j) * ld + c0);
+      } else {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) p[i][v] = c0 + v < Ns ? (MT)pd[c0 + v] : (MT)0;
+      }
 #pragma unroll
       for (int j = 0; j < TN; ++j) {
         const int r = f.col(j);
-        const f4 b = *reinterpret_cast<const f4*>(Bc + (int64_t)r * ld + c0);
+        const f4 b = BATCH ? bq[j] : *reinterpret_cast<const f4*>(Bc + (int64_t)r * ld + c0);
         MT w[4];
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          w[v] = (MT)b[v] * ((MT)acc[i][j][v] - p[v]);
+          w[v] = (MT)b[v] * ((MT)acc[i][j][v] - p[i][v]);
           rs[j] += (double)w[v];
         }
         if constexpr (sizeof(CT) == 4) {
