@@ -343,9 +343,8 @@ __device__ inline void dma16(const void* g, void* lds_base) {
 // 42, N = 5000).  Otherwise the split is blockIdx.z and the tiles of a split
 // are remapped only when their count is a multiple of 8 (the FP32 GEMM 2 on
 // 128 x 128 tiles, 14 x 158 x splits, measured 17% slower with the general
-// remap).  Within a
-// split, tiles are grouped by 8 tile rows, so tiles that run together on an
-// XCD share operand rows in its L2.
+// remap).  Within a split, tiles are grouped by 8 tile rows, so tiles that
+// run together on an XCD share operand rows in its L2.
 template <bool ALL>
 __device__ inline void tile_coords(int& tm, int& tn, int& tz) {
   const int nt_n = gridDim.x, nt_m = gridDim.y;
