@@ -100,8 +100,11 @@ def test_mvm_fp64_forces_label_vector(ffk, ctx):
 
 
 @pytest.mark.parametrize("prec,tol", [("fp32", 1e-6), ("bf16x3", 1e-6), ("bf16", 3e-3)])
-@pytest.mark.parametrize("M,N", [(7, 300), (21, 150)])
+@pytest.mark.parametrize("M,N", [(7, 300), (21, 150), (4, 1), (3, 2), (3, 129), (5, 65)])
 def test_mvm_reduced_precision(ffk, ctx, prec, tol, M, N):
+    """Reduced-precision products against the FP64 oracle, down to the
+    degenerate shapes: one geometry (one kernel block, d = 0 so only the
+    a(0) term), three atoms (D = 3), and source counts one past a tile."""
     print("mvm", prec, M, N, flush=True)
     s = system(M, N, 200 + M + N, sd=0.08)
     S = ffk.descriptor_build(ctx, dev(s.R), SIGMA)
