@@ -152,32 +152,6 @@ __global__ __launch_bounds__(64) void k_tri_inverse(const double* A, int jb, int
   for (int r = 0; r < NB; ++r) X[r * NB + c] = x[r];
 }
 
-int64_t potrf_lower(double* A, int64_t n, int64_t lda, hipStream_t st) {
-  DBuf info(8), Xinv(NB * NB * 8);
-  const unsigned long long none = ~0ull;
-  HIPCHK(hipMemcpyAsync(info.get(), &none, 8, hipMemcpyHostToDevice, st));
-  for (int64_t j0 = 0; j0 < n; j0 += NB) {
-    const int jb = (int)std::min<int64_t>(NB, n - j0);
-    k_potf2<<<1, 256, 0, st>>>(A + j0 + j0 * lda, jb, lda, j0, info.as<int64_t>());
-    LAUNCHCHK();
-    const int64_t rest = n - j0 - jb;
-    if (rest > 0) {
-      // panel <- panel L_jj^-T  (in place: one 128-row tile covers all jb columns)
-      k_tri_inverse<<<1, 64, 0, st>>>(A + j0 + j0 * lda, jb, lda, Xinv.as<double>());
-      LAUNCHCHK();
-      double* P = A + (j0 + jb) + j0 * lda;
-      gemm64((int)rest, jb, jb, 1.0, View64{P, 1, lda}, View64{Xinv.as<double>(), NB, 1}, 0.0, P, 1, lda, false, st);
-      double* C = A + (j0 + jb) + (j0 + jb) * lda;
-      gemm64((int)rest, (int)rest, jb, -1.0, View64{P, 1, lda}, View64{P, 1, lda}, 1.0, C, 1, lda, true, st);
-    }
-  }
-  unsigned long long h = 0;
-  HIPCHK(hipMemcpyAsync(&h, info.get(), 8, hipMemcpyDeviceToHost, st));
-  HIPCHK(hipStreamSynchronize(st));
-  return h == none ? -1 : (int64_t)h;
-}
-
-// ------------------------------------------------ triangular inversion ----
 // In-place inverse of a jb x jb lower-triangular diagonal block.
 __global__ __launch_bounds__(64) void k_trtri_small(double* A, int jb, int64_t lda) {
   __shared__ double L[NB][NB + 1];
@@ -204,9 +178,12 @@ __global__ __launch_bounds__(64) void k_trtri_small(double* A, int jb, int64_t l
   }
 }
 
-void trtri_lower(double* A, int64_t n, int64_t lda, hipStream_t st) {
+// In-place inverse of the lower-triangular A (n x n, lda) in 64-wide blocks,
+// last block first, with T ((n - 64) x 64) as scratch; entries above the
+// diagonal of each 64-wide diagonal block become zero, those further above
+// are not touched.
+static void trtri_nb(double* A, int64_t n, int64_t lda, hipStream_t st, double* T) {
   const int64_t nblk = (n + NB - 1) / NB;
-  DBuf T(std::max<int64_t>(n - NB, 1) * NB * sizeof(double));
   for (int64_t b = nblk - 1; b >= 0; --b) {
     const int64_t j0 = b * NB;
     const int jb = (int)std::min<int64_t>(NB, n - j0);
@@ -215,20 +192,125 @@ void trtri_lower(double* A, int64_t n, int64_t lda, hipStream_t st) {
       // T = X22 * A21 (X22 = already inverted trailing block, lower-triangular)
       const double* X22 = A + (j0 + jb) + (j0 + jb) * lda;
       double* A21 = A + (j0 + jb) + j0 * lda;
-      gemm64_alower((int)rest, jb, (int)rest, 1.0, View64{X22, 1, lda}, View64{A21, lda, 1}, 0.0, T.as<double>(),
-                    1, rest, st);
+      gemm64_alower((int)rest, jb, (int)rest, 1.0, View64{X22, 1, lda}, View64{A21, lda, 1}, 0.0, T, 1, rest, st);
       k_trtri_small<<<1, 64, 0, st>>>(A + j0 + j0 * lda, jb, lda);
       LAUNCHCHK();
       // A21 = -T * X11
       const double* X11 = A + j0 + j0 * lda;
-      gemm64((int)rest, jb, jb, -1.0, View64{T.as<double>(), 1, rest}, View64{X11, lda, 1}, 0.0, A21, 1, lda,
-             false, st);
+      gemm64((int)rest, jb, jb, -1.0, View64{T, 1, rest}, View64{X11, lda, 1}, 0.0, A21, 1, lda, false, st);
     } else {
       k_trtri_small<<<1, 64, 0, st>>>(A + j0 + j0 * lda, jb, lda);
       LAUNCHCHK();
     }
   }
-  HIPCHK(hipStreamSynchronize(st));   // T is released on return
+}
+
+// Zero the entries above the diagonal of the n x n block A (lda).
+__global__ void k_zero_upper(double* A, int64_t lda, int n) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)n * n) return;
+  const int r = (int)(e % n), c = (int)(e / n);
+  if (r < c) A[r + c * lda] = 0.0;
+}
+
+// Right-looking Cholesky in 64-wide panels on the block A (n x n, lda); the
+// first failing column (offset by j_off) goes to info.
+static void potrf_nb(double* A, int64_t n, int64_t lda, int64_t j_off, int64_t* info, double* Xinv,
+                     hipStream_t st) {
+  for (int64_t j0 = 0; j0 < n; j0 += NB) {
+    const int jb = (int)std::min<int64_t>(NB, n - j0);
+    k_potf2<<<1, 256, 0, st>>>(A + j0 + j0 * lda, jb, lda, j_off + j0, info);
+    LAUNCHCHK();
+    const int64_t rest = n - j0 - jb;
+    if (rest > 0) {
+      // panel <- panel L_jj^-T  (in place: one 128-row tile covers all jb columns)
+      k_tri_inverse<<<1, 64, 0, st>>>(A + j0 + j0 * lda, jb, lda, Xinv);
+      LAUNCHCHK();
+      double* P = A + (j0 + jb) + j0 * lda;
+      gemm64((int)rest, jb, jb, 1.0, View64{P, 1, lda}, View64{Xinv, NB, 1}, 0.0, P, 1, lda, false, st);
+      double* C = A + (j0 + jb) + (j0 + jb) * lda;
+      gemm64((int)rest, (int)rest, jb, -1.0, View64{P, 1, lda}, View64{P, 1, lda}, 1.0, C, 1, lda, true, st);
+    }
+  }
+}
+
+// dst (n x n, ldd) = the lower triangle of src (lda), zero above the diagonal
+__global__ void k_copy_lower(const double* __restrict__ src, int64_t lda, int n, double* __restrict__ dst,
+                             int64_t ldd) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)n * n) return;
+  const int r = (int)(e % n), c = (int)(e / n);
+  dst[r + c * ldd] = r >= c ? src[r + c * lda] : 0.0;
+}
+
+// Two levels of blocking.  With 64-wide panels every trailing update reads
+// and writes the whole trailing matrix for a K = 64 product, about 2 TB for
+// n = 31500, so the factorization ran at the speed of HBM.  Here 256-wide
+// panels are factored by the 64-wide code (diagonal block), their rows
+// below are solved against the inverted diagonal block, and the trailing
+// matrix takes one K = 256 update per panel: a quarter of the traffic, for
+// products that the matrix cores, not HBM, bound.
+int64_t potrf_lower(double* A, int64_t n, int64_t lda, hipStream_t st) {
+  constexpr int NB2 = 256;
+  DBuf info(8), Xinv(NB * NB * 8), L1((size_t)NB2 * NB2 * 8), T(std::max<int64_t>(n - NB2, 1) * NB2 * 8),
+      Ts((size_t)(NB2 - NB) * NB * 8);
+  const unsigned long long none = ~0ull;
+  HIPCHK(hipMemcpyAsync(info.get(), &none, 8, hipMemcpyHostToDevice, st));
+  for (int64_t J0 = 0; J0 < n; J0 += NB2) {
+    const int jb = (int)std::min<int64_t>(NB2, n - J0);
+    double* D = A + J0 + J0 * lda;
+    potrf_nb(D, jb, lda, J0, info.as<int64_t>(), Xinv.as<double>(), st);
+    const int64_t rest = n - J0 - jb;
+    if (rest > 0) {
+      // L1 = L_JJ^-1 (lower, zero above), T = A_21 L1^T, then A_22 -= T T^T and A_21 = T
+      k_copy_lower<<<cdiv((int64_t)jb * jb, 256), 256, 0, st>>>(D, lda, jb, L1.as<double>(), jb);
+      LAUNCHCHK();
+      trtri_nb(L1.as<double>(), jb, jb, st, Ts.as<double>());
+      double* A21 = A + (J0 + jb) + J0 * lda;
+      gemm64((int)rest, jb, jb, 1.0, View64{A21, 1, lda}, View64{L1.as<double>(), 1, jb}, 0.0, T.as<double>(), 1,
+             rest, false, st);
+      double* C = A + (J0 + jb) + (J0 + jb) * lda;
+      gemm64((int)rest, (int)rest, jb, -1.0, View64{T.as<double>(), 1, rest}, View64{T.as<double>(), 1, rest}, 1.0,
+             C, 1, lda, true, st);
+      HIPCHK(hipMemcpy2DAsync(A21, lda * 8, T.get(), rest * 8, rest * 8, jb, hipMemcpyDeviceToDevice, st));
+    }
+  }
+  unsigned long long h = 0;
+  HIPCHK(hipMemcpyAsync(&h, info.get(), 8, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return h == none ? -1 : (int64_t)h;
+}
+
+// ------------------------------------------------ triangular inversion ----
+// Two levels, as potrf_lower: 256-wide blocks, last first.  For each, T =
+// X22 A21 with the already inverted trailing block (K = rest, N = 256: a
+// quarter of the reads of X22 that 64-wide blocks needed), the diagonal block
+// inverted by the 64-wide code, then A21 = -T X11.
+void trtri_lower(double* A, int64_t n, int64_t lda, hipStream_t st) {
+  constexpr int NB2 = 256;
+  const int64_t nblk = (n + NB2 - 1) / NB2;
+  DBuf T(std::max<int64_t>(n - NB2, 1) * NB2 * sizeof(double)), Ts((NB2 - NB) * NB * sizeof(double));
+  for (int64_t b = nblk - 1; b >= 0; --b) {
+    const int64_t j0 = b * NB2;
+    const int jb = (int)std::min<int64_t>(NB2, n - j0);
+    const int64_t rest = n - j0 - jb;
+    double* D = A + j0 + j0 * lda;
+    if (rest > 0) {
+      const double* X22 = A + (j0 + jb) + (j0 + jb) * lda;
+      double* A21 = A + (j0 + jb) + j0 * lda;
+      gemm64_alower((int)rest, jb, (int)rest, 1.0, View64{X22, 1, lda}, View64{A21, lda, 1}, 0.0, T.as<double>(), 1,
+                    rest, st);
+      trtri_nb(D, jb, lda, st, Ts.as<double>());
+      // X11 enters the product below as a full block: nothing above its diagonal
+      k_zero_upper<<<cdiv((int64_t)jb * jb, 256), 256, 0, st>>>(D, lda, jb);
+      LAUNCHCHK();
+      gemm64((int)rest, jb, jb, -1.0, View64{T.as<double>(), 1, rest}, View64{D, lda, 1}, 0.0, A21, 1, lda, false,
+             st);
+    } else {
+      trtri_nb(D, jb, lda, st, Ts.as<double>());
+    }
+  }
+  HIPCHK(hipStreamSynchronize(st));   // T and Ts are released on return
 }
 
 }  // namespace ffk
