@@ -80,7 +80,7 @@ void gemm64_alower(int M, int N, int K, double alpha, View64 A, View64 B, double
   gemm64_dispatch(M, N, K, alpha, A, B, beta, C, scm, scn, false, true, st);
 }
 
-// ------------------------------------------------------------- Cholesky ----
+// ------------------------------------- Cholesky and triangular inversion ----
 constexpr int NB = 64;
 
 // Unblocked Cholesky of one jb x jb diagonal block (column-major, lda) in LDS.
@@ -281,11 +281,11 @@ int64_t potrf_lower(double* A, int64_t n, int64_t lda, hipStream_t st) {
   return h == none ? -1 : (int64_t)h;
 }
 
-// ------------------------------------------------ triangular inversion ----
-// Two levels, as potrf_lower: 256-wide blocks, last first.  For each, T =
-// X22 A21 with the already inverted trailing block (K = rest, N = 256: a
-// quarter of the reads of X22 that 64-wide blocks needed), the diagonal block
-// inverted by the 64-wide code, then A21 = -T X11.
+// In-place inverse of the lower-triangular A (n x n, lda).  Two levels, as
+// potrf_lower: 256-wide blocks, last first.  For each, T = X22 A21 with the
+// already inverted trailing block (K = rest, N = 256: a quarter of the reads
+// of X22 that 64-wide blocks needed), the diagonal block inverted by the
+// 64-wide code, then A21 = -T X11.
 void trtri_lower(double* A, int64_t n, int64_t lda, hipStream_t st) {
   constexpr int NB2 = 256;
   const int64_t nblk = (n + NB2 - 1) / NB2;
