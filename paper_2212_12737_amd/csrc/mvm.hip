@@ -59,7 +59,12 @@ __global__ __launch_bounds__(256) void k_jv_tile(const double* __restrict__ R, c
     const int pq = pairs[d];
     const int p = 3 * (pq >> 16), q = 3 * (pq & 0xFFFF);
     double cs = 0.0;
-    double ug[GT];
+    double ug[GT], xg[GT];
+    // the group's descriptor entries first: all GT loads in flight before
+    // the first use (loaded inside the per-geometry branch below, each was
+    // waited on in turn)
+#pragma unroll
+    for (int gl = 0; gl < GT; ++gl) xg[gl] = gl < ng ? Xc[(g0 + gl) * D + d] : 0.0;
 #pragma unroll
     for (int gl = 0; gl < GT; ++gl) {
       double u = 0.0;
@@ -69,7 +74,7 @@ __global__ __launch_bounds__(256) void k_jv_tile(const double* __restrict__ R, c
         const double dx = Rg[p] - Rg[q], dy = Rg[p + 1] - Rg[q + 1], dz = Rg[p + 2] - Rg[q + 2];
         const double ir = 1.0 / sqrt(dx * dx + dy * dy + dz * dz);
         u = -(dx * (vg[p] - vg[q]) + dy * (vg[p + 1] - vg[q + 1]) + dz * (vg[p + 2] - vg[q + 2])) * (ir * ir * ir);
-        pdp[gl] += u * Xc[(g0 + gl) * D + d];
+        pdp[gl] += u * xg[gl];
         const int64_t o = (g0 + gl) * ldu + d;
         if (MODE == 0) static_cast<double*>(U)[o] = u;
         if (MODE == 1) static_cast<float*>(U)[o] = (float)u;
@@ -183,27 +188,20 @@ __device__ inline double block_sum_waves(double x) {
   return t;
 }
 
-// Whether a geometry's descriptor row is staged in LDS beside its coordinates
-// and its row of G: while the block needs at most 20 KB, so that eight
-// blocks of four waves still share a CU (M up to about 50).  The J^T G
-// kernels wait on their loads: at M = 42, N = 5000 the staged row took the
-// reduce from 61.8 to 57.1 us; at M = 60, N = 20000 (29.8 KB, five blocks
-// per CU) it took it from 344 to 428 us.
-static inline bool jtg_stage_x(int M, int64_t D) { return (3 * M + 2 * D) * (int64_t)sizeof(double) <= 20480; }
-
 // y_g = J_g^T G_g + shift v_g, one geometry per block.
 // y = J^T G + shift v for geometry g from its coordinates sR (3M) and its
 // row sG (D) of G, both in LDS.  With vy_part (and v), also v_g . y_g into
-// vy_part[g]: the block partials of v^T y, which CG needs as p^T q.  The
-// inverse distance of a pair is its descriptor entry: given sX (the
-// geometry's descriptor row in LDS) it is read rather than recomputed with
-// an FP64 square root and divide per pair.
+// vy_part[g]: the block partials of v^T y, which CG needs as p^T q.  Pair
+// (a, b) adds -G_ab x_ab^3 (r_a - r_b) to atom a, x_ab = 1 / |r_a - r_b| its
+// descriptor entry; the row sG arrives already scaled, G_ab x_ab^3 (the
+// callers form it from the descriptor row as they fill sG), so the loop over
+// partners needs no square root or divide.
 // Each atom takes a group of L lanes (a power of two, within a wave, as many
 // as the block holds for all M atoms): lane `part` sums the partners b =
 // part, part + L, ..., and the group's sums meet in a fixed butterfly, so
 // the result does not depend on timing.  (One lane per atom left most of the
 // block idle behind a serial loop over M - 1 partners.)
-__device__ inline void jtg_atoms(const double* sR, const double* sG, const double* sX, int64_t g, int M,
+__device__ inline void jtg_atoms(const double* sR, const double* sG, int64_t g, int M,
                                  const double* v, double shift, double* y, bool accumulate = false,
                                  double* vy_part = nullptr) {
   int L = 1;
@@ -220,8 +218,7 @@ __device__ inline void jtg_atoms(const double* sR, const double* sG, const doubl
         if (b == a) continue;
         const int idx = a > b ? a * (a - 1) / 2 + b : b * (b - 1) / 2 + a;
         const double dx = xa - sR[3 * b], dy = ya - sR[3 * b + 1], dz = za - sR[3 * b + 2];
-        const double ir = sX ? sX[idx] : 1.0 / sqrt(dx * dx + dy * dy + dz * dz);
-        const double c = sG[idx] * ir * ir * ir;
+        const double c = sG[idx];
         ax -= c * dx;
         ay -= c * dy;
         az -= c * dz;
@@ -258,22 +255,21 @@ __device__ inline void jtg_atoms(const double* sR, const double* sG, const doubl
 }
 
 // y = J^T G + shift v, or y += J^T G with accumulate (then v is unused).
-// X: the uncentred descriptor rows, staged in LDS after G when given.
+// X: the uncentred descriptor rows, which scale G as it is staged.
 __global__ void k_jtg(const double* __restrict__ R, const double* __restrict__ G, const double* __restrict__ X,
                       const double* __restrict__ v, double shift, int M, int64_t D,
                       double* __restrict__ y, int accumulate = 0, double* __restrict__ vy_part = nullptr) {
   extern __shared__ double sm[];
   double* sR = sm;
   double* sG = sm + 3 * M;
-  double* sX = X ? sG + D : nullptr;
   const int64_t g = blockIdx.x;
   for (int i = threadIdx.x; i < 3 * M; i += blockDim.x) sR[i] = R[g * 3 * M + i];
   for (int64_t i = threadIdx.x; i < D; i += blockDim.x) {
-    sG[i] = G[g * D + i];
-    if (X) sX[i] = X[g * D + i];
+    const double x = X[g * D + i];
+    sG[i] = G[g * D + i] * (x * x * x);
   }
   __syncthreads();
-  jtg_atoms(sR, sG, sX, g, M, accumulate ? nullptr : v, shift, y, accumulate != 0,
+  jtg_atoms(sR, sG, g, M, accumulate ? nullptr : v, shift, y, accumulate != 0,
             accumulate ? nullptr : vy_part);
 }
 
@@ -289,9 +285,15 @@ __device__ inline double wave_sum_parts(const double* __restrict__ p, int n) {
 
 // The split-K reduction of GEMM 2 fused with J^T G: one block per geometry
 // forms its row of G = sum_z part_z + a0 s + w Xt in LDS (the arithmetic and
-// order of k_g_reduce) and applies J^T to it; G never goes to HBM.
-// With xmean, the descriptor row x = x_c + mean is staged after G in LDS.
-template <typename PT>
+// order of k_g_reduce) and applies J^T to it; G never goes to HBM.  The
+// row is staged already scaled by x^3, with the descriptor x = x_c + mean
+// recovered from the centred row the reduction reads anyway.
+// SPL: the number of splits when fixed at compile time (1 to 8), else 0.  A
+// thread takes CC columns at a time (1 while a block's lanes cover the row,
+// else 2) and, with SPL fixed, issues every load of them before the first
+// wait (with the count known only at run time the loads of each split were
+// waited on in turn).  LDS: 3M + D + 1 doubles.
+template <typename PT, int SPL, int CC>
 __global__ void k_jtg_reduce(const PT* __restrict__ part, int splits, int64_t rows, const double* __restrict__ s,
                              const double* __restrict__ Xt, const double* __restrict__ xmean,
                              const double* __restrict__ wpart, int ntn, double a0,
@@ -300,7 +302,6 @@ __global__ void k_jtg_reduce(const PT* __restrict__ part, int splits, int64_t ro
   extern __shared__ double sm[];
   double* sR = sm;
   double* sG = sm + 3 * M;
-  double* sX = xmean ? sG + D : nullptr;
   __shared__ double wsh;
   const int64_t g = blockIdx.x;
   if (threadIdx.x < 64) {
@@ -310,16 +311,71 @@ __global__ void k_jtg_reduce(const PT* __restrict__ part, int splits, int64_t ro
   for (int i = threadIdx.x; i < 3 * M; i += blockDim.x) sR[i] = R[g * 3 * M + i];
   __syncthreads();
   const double w = wsh;
-  for (int64_t c = threadIdx.x; c < D; c += blockDim.x) {
-    double acc = 0.0;
+  const int64_t bd = blockDim.x, zs = rows * D;
+  for (int64_t cb = threadIdx.x; cb < D; cb += CC * bd) {
+    double xc[CC], sc[CC], xm[CC], acc[CC];
+#pragma unroll
+    for (int j = 0; j < CC; ++j) {
+      const int64_t c = min(cb + j * bd, D - 1);   // a column past the end reads D - 1
+      xc[j] = Xt[g * D + c];
+      sc[j] = s[c];
+      xm[j] = xmean[c];
+    }
+    if constexpr (SPL > 0) {
+      PT pz[CC][SPL];
+#pragma unroll
+      for (int j = 0; j < CC; ++j)
+#pragma unroll
+        for (int z = 0; z < SPL; ++z) pz[j][z] = part[g * D + min(cb + j * bd, D - 1) + z * zs];
+#pragma unroll
+      for (int j = 0; j < CC; ++j) {
+        acc[j] = 0.0;
+#pragma unroll
+        for (int z = 0; z < SPL; ++z) acc[j] += (double)pz[j][z];
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < CC; ++j) {
+        const int64_t c = min(cb + j * bd, D - 1);
+        acc[j] = 0.0;
 #pragma unroll 4
-    for (int z = 0; z < splits; ++z) acc += (double)part[((int64_t)z * rows + g) * D + c];
-    const double xc = Xt[g * D + c];
-    sG[c] = acc + a0 * s[c] + w * xc;
-    if (xmean) sX[c] = xc + xmean[c];
+        for (int z = 0; z < splits; ++z) acc[j] += (double)part[g * D + c + z * zs];
+      }
+    }
+    // no branch here (the loads would sink into it): a column of the thread
+    // past the end goes to the spare slot sG[D]
+#pragma unroll
+    for (int j = 0; j < CC; ++j) {
+      const double x = xc[j] + xm[j];
+      sG[min(cb + j * bd, D)] = (acc[j] + a0 * sc[j] + w * xc[j]) * (x * x * x);
+    }
   }
   __syncthreads();
-  jtg_atoms(sR, sG, sX, g, M, v, shift, y, false, vy_part);
+  jtg_atoms(sR, sG, g, M, v, shift, y, false, vy_part);
+}
+
+template <typename PT, int CC, typename... A>
+static void launch_jtg_reduce_cc(int64_t N, size_t shm, hipStream_t st, const PT* part, int splits, A... args) {
+  switch (splits) {
+    case 1: k_jtg_reduce<PT, 1, CC><<<N, 256, shm, st>>>(part, splits, args...); break;
+    case 2: k_jtg_reduce<PT, 2, CC><<<N, 256, shm, st>>>(part, splits, args...); break;
+    case 3: k_jtg_reduce<PT, 3, CC><<<N, 256, shm, st>>>(part, splits, args...); break;
+    case 4: k_jtg_reduce<PT, 4, CC><<<N, 256, shm, st>>>(part, splits, args...); break;
+    case 5: k_jtg_reduce<PT, 5, CC><<<N, 256, shm, st>>>(part, splits, args...); break;
+    case 6: k_jtg_reduce<PT, 6, CC><<<N, 256, shm, st>>>(part, splits, args...); break;
+    case 7: k_jtg_reduce<PT, 7, CC><<<N, 256, shm, st>>>(part, splits, args...); break;
+    case 8: k_jtg_reduce<PT, 8, CC><<<N, 256, shm, st>>>(part, splits, args...); break;
+    default: k_jtg_reduce<PT, 0, CC><<<N, 256, shm, st>>>(part, splits, args...); break;
+  }
+}
+
+template <typename PT, typename... A>
+static void launch_jtg_reduce(int64_t N, int64_t D, size_t shm, hipStream_t st, const PT* part, int splits,
+                              A... args) {
+  if (D <= 256)
+    launch_jtg_reduce_cc<PT, 1>(N, shm, st, part, splits, args...);
+  else
+    launch_jtg_reduce_cc<PT, 2>(N, shm, st, part, splits, args...);
 }
 
 // ------------------------------------------------------------- epilogues ----
@@ -945,25 +1001,20 @@ static void kernel_mvm_core(ffk_system* t, ffk_system* src, CoeffSet* coef, cons
   }
   mark(ev, 4, st);
   const int tb = M <= 64 ? 64 : 128;
-  const bool stage = jtg_stage_x(M, D);
-  const size_t shj = (3 * M + (stage ? 2 : 1) * D) * sizeof(double);
-  const double* xm = stage ? t->xmean.as<double>() : nullptr;
+  const size_t shj = (3 * M + D + 1) * sizeof(double);
+  const double* xm = t->xmean.as<double>();
   clk_begin(CLK_JTG, st);
   if (go.splits < 0)
-    k_jtg_reduce<float><<<N, 256, shj, st>>>(static_cast<const float*>(b.part), -go.splits, N, b.s,
-                                            t->Xc.as<double>(), xm, b.wpart, go.ntn, t->a0, t->R.as<double>(),
-                                            v, shift, M, D, y, vy_part);
+    launch_jtg_reduce(N, D, shj, st, static_cast<const float*>(b.part), -go.splits, N, b.s, t->Xc.as<double>(), xm,
+                      b.wpart, go.ntn, t->a0, t->R.as<double>(), v, shift, M, D, y, vy_part);
   else if (go.splits == 1)
-    k_jtg<<<N, tb, shj, st>>>(t->R.as<double>(), b.G, stage ? t->X.as<double>() : nullptr, v, shift, M, D, y, 0,
-                              vy_part);
+    k_jtg<<<N, tb, shj, st>>>(t->R.as<double>(), b.G, t->X.as<double>(), v, shift, M, D, y, 0, vy_part);
   else if (prec == FFK_FP64)
-    k_jtg_reduce<double><<<N, 256, shj, st>>>(static_cast<const double*>(b.part), go.splits, N, b.s,
-                                             t->Xc.as<double>(), xm, b.wpart, go.ntn, t->a0, t->R.as<double>(),
-                                             v, shift, M, D, y, vy_part);
+    launch_jtg_reduce(N, D, shj, st, static_cast<const double*>(b.part), go.splits, N, b.s, t->Xc.as<double>(), xm,
+                      b.wpart, go.ntn, t->a0, t->R.as<double>(), v, shift, M, D, y, vy_part);
   else
-    k_jtg_reduce<float><<<N, 256, shj, st>>>(static_cast<const float*>(b.part), go.splits, N, b.s,
-                                            t->Xc.as<double>(), xm, b.wpart, go.ntn, t->a0, t->R.as<double>(),
-                                            v, shift, M, D, y, vy_part);
+    launch_jtg_reduce(N, D, shj, st, static_cast<const float*>(b.part), go.splits, N, b.s, t->Xc.as<double>(), xm,
+                      b.wpart, go.ntn, t->a0, t->R.as<double>(), v, shift, M, D, y, vy_part);
   LAUNCHCHK();
   clk_end(CLK_JTG, st);
   mark(ev, 5, st);
@@ -1214,10 +1265,8 @@ void rect_mvm(const ffk_system* tr, const ffk_system* te, const double* alpha, d
   mvm_gemms_scalar<double>(a, c.Xt.as<double>(), tr->Xc.as<double>(), c.U.as<double>(), c.dA.as<double>(),
                            c.B.as<double>(), c.Wn.as<double>(), st, nullptr);
   const int tb = M <= 64 ? 64 : 128;
-  const bool stage = jtg_stage_x(M, D);
-  k_jtg<<<Nt, tb, (3 * M + (stage ? 2 : 1) * D) * sizeof(double), st>>>(
-      te->R.as<double>(), c.G.as<double>(), stage ? te->X.as<double>() : nullptr, shift_v, shift, M, D, F,
-      accumulate ? 1 : 0);
+  k_jtg<<<Nt, tb, (3 * M + D) * sizeof(double), st>>>(te->R.as<double>(), c.G.as<double>(), te->X.as<double>(),
+                                                      shift_v, shift, M, D, F, accumulate ? 1 : 0);
   LAUNCHCHK();
   if (!cache) HIPCHK(hipStreamSynchronize(st));   // the temporaries are freed on return
 }
