@@ -116,6 +116,24 @@ def test_mvm_reduced_precision(ffk, ctx, prec, tol, M, N):
     assert err <= tol
 
 
+@pytest.mark.parametrize("M,N", [(25, 1100), (42, 600)])
+def test_mvm_long_descriptor_rows(ffk, ctx, M, N):
+    """Descriptor rows longer than one block's 256 lanes (D = 300, and the
+    odd D = 861), where the J^T G reduction takes two columns per thread and
+    the last pair runs past the row's end; several GEMM tiles with a ragged
+    tail.  The whole output, every precision, against the FP64 oracle."""
+    s = system(M, N, 500 + M + N, sd=0.08)
+    S = ffk.descriptor_build(ctx, dev(s.R), SIGMA)
+    v = synth.random_vectors(S.n, 9)
+    ref = ok.kernel_mvm(s.R, s.R, v, SIGMA)
+    for prec, tol in [("fp64", 1e-10), ("fp32", 1e-6), ("bf16x3", 1e-6), ("bf16", 3e-3)]:
+        print("mvm", prec, M, N, flush=True)
+        y = host(ffk.kernel_mvm(ctx, S, dev(v), prec=ffk.PRECISIONS[prec]))
+        err = relerr(y, ref)
+        print("relerr", prec, err, flush=True)
+        assert err <= tol
+
+
 def test_predict_matches_oracle(ffk, ctx):
     tr = synth.make_system(8, 170, 0.05, True, 31, 32, 33)
     te = synth.make_system(8, 37, 0.05, True, 31, 34, 33)
