@@ -155,7 +155,9 @@ static void launch_jv(int64_t N, int M, hipStream_t st, A... args) {
 
 // s = sum of the per-block column partials (nblk x D): one wave per column,
 // four columns per block; lane l takes partials l, l + 64, ... and a fixed
-// butterfly combines the lanes.
+// butterfly combines the lanes.  (Eight loads per lane in flight, with the
+// ones past the end clamped and masked, made it slower at M = 60, N = 20000:
+// 16.5 -> 19.9 us; at N = 2000 it sits at a 6 us floor either way.)
 __global__ __launch_bounds__(256) void k_colsum_final(const double* __restrict__ part, int nblk, int64_t D,
                                                       double* __restrict__ s) {
   const int64_t col = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -288,7 +290,7 @@ __device__ inline double wave_sum_parts(const double* __restrict__ p, int n) {
 // order of k_g_reduce) and applies J^T to it; G never goes to HBM.  The
 // row is staged already scaled by x^3, with the descriptor x = x_c + mean
 // recovered from the centred row the reduction reads anyway.
-// SPL: the number of splits when fixed at compile time (1 to 8), else 0.  A
+// SPL: the number of splits when fixed at compile time (1 to 8, 16), else 0.  A
 // thread takes CC columns at a time (1 while a block's lanes cover the row,
 // else 2) and, with SPL fixed, issues every load of them before the first
 // wait (with the count known only at run time the loads of each split were
@@ -322,16 +324,23 @@ __global__ void k_jtg_reduce(const PT* __restrict__ part, int splits, int64_t ro
       xm[j] = xmean[c];
     }
     if constexpr (SPL > 0) {
-      PT pz[CC][SPL];
+      // at most eight splits' loads in flight: sixteen 64-bit addresses
+      // and values per column do not fit the 64 VGPRs of full occupancy
+      constexpr int ZB = SPL < 8 ? SPL : 8;
+      static_assert(SPL % ZB == 0, "split batches");
 #pragma unroll
-      for (int j = 0; j < CC; ++j)
+      for (int j = 0; j < CC; ++j) acc[j] = 0.0;
+#pragma unroll 1
+      for (int z0 = 0; z0 < SPL; z0 += ZB) {
+        PT pz[CC][ZB];
 #pragma unroll
-        for (int z = 0; z < SPL; ++z) pz[j][z] = part[g * D + min(cb + j * bd, D - 1) + z * zs];
+        for (int j = 0; j < CC; ++j)
 #pragma unroll
-      for (int j = 0; j < CC; ++j) {
-        acc[j] = 0.0;
+          for (int z = 0; z < ZB; ++z) pz[j][z] = part[g * D + min(cb + j * bd, D - 1) + (z0 + z) * zs];
 #pragma unroll
-        for (int z = 0; z < SPL; ++z) acc[j] += (double)pz[j][z];
+        for (int j = 0; j < CC; ++j)
+#pragma unroll
+          for (int z = 0; z < ZB; ++z) acc[j] += (double)pz[j][z];
       }
     } else {
 #pragma unroll
@@ -365,6 +374,7 @@ static void launch_jtg_reduce_cc(int64_t N, size_t shm, hipStream_t st, const PT
     case 6: k_jtg_reduce<PT, 6, CC><<<N, 256, shm, st>>>(part, splits, args...); break;
     case 7: k_jtg_reduce<PT, 7, CC><<<N, 256, shm, st>>>(part, splits, args...); break;
     case 8: k_jtg_reduce<PT, 8, CC><<<N, 256, shm, st>>>(part, splits, args...); break;
+    case 16: k_jtg_reduce<PT, 16, CC><<<N, 256, shm, st>>>(part, splits, args...); break;
     default: k_jtg_reduce<PT, 0, CC><<<N, 256, shm, st>>>(part, splits, args...); break;
   }
 }
