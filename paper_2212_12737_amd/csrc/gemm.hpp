@@ -659,11 +659,11 @@ template <typename PT> struct EpiPart {
   }
 };
 
-// Number of K splits that brings a GEMM with `tiles` output tiles to >= 512
-// workgroups while keeping at least two K tiles per split.
-inline int pick_splits(int64_t tiles, int64_t ktiles) {
+// Number of K splits that brings a GEMM with `tiles` output tiles to >=
+// `target` workgroups while keeping at least two K tiles per split.
+inline int pick_splits(int64_t tiles, int64_t ktiles, int64_t target = 512) {
   int s = 1;
-  while (tiles * s < 512 && (int64_t)s * 4 <= ktiles) s *= 2;
+  while (tiles * s < target && (int64_t)s * 4 <= ktiles) s *= 2;
   return s;
 }
 

@@ -712,7 +712,13 @@ struct DmaOps {
 };
 
 // K splits for GEMM 2.  A grid smaller than the workgroup slots of the GPU
-// takes the fixed rule of pick_splits.  A larger grid takes the split count
+// takes the fixed rule of pick_splits: at least 512 workgroups, or 256 for
+// BF16 and FP32 operands below N = 4096, where the products are latency-bound
+// and half the partials cost more than half the parallelism.  (At M = 21,
+// N = 2000, 8 splits instead of 16: split BF16 61.6 -> 56.2 us, BF16 44.8 ->
+// 41.5, FP32 98.5 -> 95.7; FP64 went 169.5 -> 187.0 and keeps 16.  At
+// N = 5000 and 10000 the lower target was up to 22% slower.)  A larger grid
+// takes the split count
 // that minimises the estimated time: ceil(tiles s / slots) rounds of 1/s of
 // the K loop each, plus the split-K partials written and read back once.
 // Without it, 553 tiles of 256 x 256 on 256 slots run 3 rounds for 2.16
@@ -730,7 +736,7 @@ static int gemm2_splits(int64_t tiles, int64_t ktiles, int64_t N, int64_t D) {
     per_cu = nb > 0 ? nb : 1;
   }
   const int64_t slots = (int64_t)cus * per_cu;
-  if (tiles < slots) return pick_splits(tiles, ktiles);
+  if (tiles < slots) return pick_splits(tiles, ktiles, sizeof(T) <= 4 && N < 4096 ? 256 : 512);
   const double rate_cu = (sizeof(T) == 2 ? 1.2e15 : sizeof(T) == 4 ? 1.15e14 : 5.0e13) / 256.0;
   const double t_tile = 2.0 * TL::BM * TL::BN * (double)ktiles * (64 / sizeof(T)) * (X3 ? 3 : 1) / rate_cu;
   const double t_part = 2.0 * (double)N * D * sizeof(CT) / 5.0e12;
