@@ -820,6 +820,12 @@ static GemmOut mvm_gemms_dma(const MvmArgs& a, int64_t Ntr, int64_t Nsr, int64_t
 // (hi and lo operands) fills a CU either way and takes the larger tile
 // below.  FP32 and FP64 stay at 128 x 128, which measured faster.
 typedef DmaTile<64, 64, 2, 2, 4> TileM;        // GEMM 1 of small N: 4x more workgroups
+// The same tile in split BF16 with two stages: its hi and lo operands take 16
+// KB a stage, so four stages held a CU to two workgroups, and at N = 2000
+// (seven K steps) the 1024 tiles ran in two rounds.  GEMM 1 19.9 -> 17.6 us
+// at M = 21, N = 2000; single BF16 (14.4 against 13.4 us), FP32 and FP64
+// keep four stages.
+typedef DmaTile<64, 64, 2, 2, 2> TileMX3;
 typedef DmaTile<128, 128, 2, 2, 4> TileS;
 typedef DmaTile<256, 128, 4, 2, 3> TileL;      // BF16 and split BF16, large N
 typedef DmaTile<64, 256, 1, 4, 3> TileW2;      // GEMM 2 of small N: one tile spans D <= 256 columns
@@ -845,6 +851,8 @@ static GemmOut mvm_gemms_for(const MvmArgs& a, int64_t Ntr, int64_t Nsr, int64_t
     // BF16: one 256-wide GEMM 2 tile reads [dA | -W] once instead of once per
     // 128 columns (split BF16 at N = 2000, D = 210: 30 -> 27 us); FP32 and
     // FP64 measured 2% slower with it
+    if constexpr (sizeof(T) == 2 && X3)
+      return mvm_gemms_dma<T, X3, CT, TileMX3, TileW2>(a, Ntr, Nsr, Dk, Dr, o, st, ev);
     if constexpr (sizeof(T) == 2) return mvm_gemms_dma<T, X3, CT, TileM, TileW2>(a, Ntr, Nsr, Dk, Dr, o, st, ev);
     return mvm_gemms_dma<T, X3, CT, TileM, TileS>(a, Ntr, Nsr, Dk, Dr, o, st, ev);
   } else if constexpr (sizeof(T) == 2 && X3) {
