@@ -134,6 +134,22 @@ def test_mvm_long_descriptor_rows(ffk, ctx, M, N):
         assert err <= tol
 
 
+@pytest.mark.parametrize("M,N", [(21, 2000), (25, 1100), (42, 600), (42, 5000)])
+def test_mvm_repeats_bit_for_bit(ffk, ctx, M, N):
+    """Every reduction of the two-GEMM product has a fixed order (no
+    floating-point atomics), so repeated products agree bit for bit in every
+    precision.  The shapes reach 16 and 8 K splits of GEMM 2 at small N, the
+    two-column J^T G reduction (D = 300, 861), and the large tiles."""
+    s = system(M, N, 700 + M + N, sd=0.08)
+    S = ffk.descriptor_build(ctx, dev(s.R), SIGMA)
+    v = dev(synth.random_vectors(S.n, 11))
+    for prec in ("fp64", "fp32", "bf16x3", "bf16"):
+        print("repeat", prec, M, N, flush=True)
+        y1 = host(ffk.kernel_mvm(ctx, S, v, prec=ffk.PRECISIONS[prec]))
+        y2 = host(ffk.kernel_mvm(ctx, S, v, prec=ffk.PRECISIONS[prec]))
+        assert np.array_equal(y1, y2), prec
+
+
 def test_predict_matches_oracle(ffk, ctx):
     tr = synth.make_system(8, 170, 0.05, True, 31, 32, 33)
     te = synth.make_system(8, 37, 0.05, True, 31, 34, 33)
